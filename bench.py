@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark: QMC least-squares American pricing throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--dtype fp32]
+
+A step is one full pricing call (Sobol -> inverse normal -> bridge -> GBM
+paths -> backward induction -> discounted mean) on the configuration's inputs,
+enqueued through the C-ABI on one stream with a torch-owned workspace.  Inputs
+(paths) are produced on the device by the call itself; nothing crosses PCIe in
+the timed region except the 16-byte result of the last step.  Prints one JSON
+line.
+
+Default workload: the single American put S0=K=100, r=0.05, sigma=0.3, T=1,
+100 dates, 2^20 Sobol paths, weighted Laguerre degree 3, FP32 bulk with FP64
+solve (the FP64 run of the same workload is reported beside it).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4])
+    ap.add_argument("--dtype", default=None, choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-side", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(amq, pricer, p, b, w, dtype, steps, warmup):
+    import torch
+    n_bytes = amq.am_workspace_bytes(w.n_paths, w.n_dates, b, dtype)
+    ws = pricer.workspace(n_bytes)
+    for _ in range(warmup):
+        amq.am_price_american_ex(p, w.n_paths, w.n_dates, b, dtype, ws, pricer.stream, wait=False)
+    torch.cuda.synchronize()
+    amq.am_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        amq.am_price_american_ex(p, w.n_paths, w.n_dates, b, dtype, ws, pricer.stream, wait=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gen_ms, sweep_ms, calls = amq.am_profile_read()
+    amq.am_profile_enable(False)
+    res = pricer.views(w.n_paths, w.n_dates, b, dtype)["result"].cpu().numpy()
+    return dict(seconds=t1 - t0, gen_ms=gen_ms / calls, sweep_ms=sweep_ms / calls,
+                price=float(res[0]), std_err=float(res[1]))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(w):
+    """The FP64 oracle, single-threaded, on the first paths of the workload."""
+    import oracle
+    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    # bounded sample, about 10-15 s of single-threaded work
+    if w.n_paths >= (1 << 24):
+        n = 1 << 18
+    elif w.n_paths >= (1 << 20):
+        n = w.n_paths // 2
+    else:
+        n = w.n_paths
+    kind = oracle.LAGUERRE if w.basis[0] == "laguerre" else oracle.MONOMIAL
+    t0 = time.perf_counter()
+    r = oracle.price_american(**w.params(), N=n, M=w.n_dates, is_call=w.is_call,
+                              allow_exercise=w.allow_exercise, kind=kind, degree=w.basis[1])
+    dt = time.perf_counter() - t0
+    return dict(value=n * w.n_dates / dt, unit="path-steps/s", cores=1, kind="oracle",
+                sample=f"first {n} of {w.n_paths} paths x {w.n_dates} dates of the same workload "
+                       f"(FP64, single thread, {dt:.1f} s, {cpu_model()}, nproc {os.cpu_count()})",
+                price_on_sample=r.price)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+    import torch
+    import paper_1205_0106_amd as amq
+    from paper_1205_0106_amd.workloads import CONFIGS
+
+    w = CONFIGS[args.config]
+    dtype = args.dtype or ("fp32" if "fp32" in w.dtypes else "fp64")
+    p = amq.make_params(**w.params(), is_call=w.is_call, allow_exercise=w.allow_exercise)
+    b = amq.make_basis(*w.basis)
+    pricer = amq.Pricer(0)
+    path_steps = w.n_paths * w.n_dates
+
+    m = time_steps(amq, pricer, p, b, w, dtype, args.steps, args.warmup)
+    value = path_steps * args.steps / m["seconds"]
+    s = 4 if dtype == "fp32" else 8
+
+    # dominant kernel and its roofline (algorithmic bytes: generation writes
+    # every path value once, the sweep reads every date's slab once)
+    alg_bytes = path_steps * s
+    if m["sweep_ms"] >= m["gen_ms"]:
+        dom, ms = "sweep", m["sweep_ms"]
+    else:
+        dom, ms = "generate", m["gen_ms"]
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None,
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms, 4)}
+
+    out = {
+        "metric": "path-steps/s for QMC-LSM American pricing",
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * m["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == "fp32" else "f64",
+        "data": "synthetic (on-device Sobol paths)",
+        "config": {"workload": w.name, "n_paths": w.n_paths, "n_dates": w.n_dates,
+                   "basis": f"{w.basis[0]} degree {w.basis[1]}",
+                   "precision": "FP32 bulk, FP64 solve and sums" if dtype == "fp32" else "FP64",
+                   "S0": w.S0, "K": w.K, "r": w.r, "sigma": w.sigma, "T": w.T},
+        "roofline": roofline,
+        "phase_ms": {"generate": round(m["gen_ms"], 4), "sweep": round(m["sweep_ms"], 4)},
+        "price": m["price"],
+        "std_err": m["std_err"],
+    }
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_config{args.config}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        out["oracle_price"] = g["price"]
+        out["abs_err_vs_oracle"] = abs(m["price"] - g["price"])
+    if dtype == "fp32" and "fp64" in w.dtypes and not args.no_fp64_side:
+        m64 = time_steps(amq, pricer, p, b, w, "fp64", max(3, args.steps // 4), 1)
+        out["fp64_side"] = {"value": path_steps * max(3, args.steps // 4) / m64["seconds"],
+                            "price": m64["price"], "phase_ms": {"generate": round(m64["gen_ms"], 4),
+                                                               "sweep": round(m64["sweep_ms"], 4)}}
+        if "oracle_price" in out:
+            out["fp64_side"]["abs_err_vs_oracle"] = abs(m64["price"] - out["oracle_price"])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    out["gpu"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

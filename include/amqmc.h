@@ -1,0 +1,166 @@
+/*
+ * amqmc.h — C-ABI of the MI355X quasi-Monte Carlo American option engine.
+ *
+ * Method: Cvetanoska & Stojanovski, "Using High Performance Computing and
+ * Monte Carlo Simulation for Pricing American Options".  One call values one
+ * option on n_paths quasi-random GBM paths observed at n_dates exercise dates:
+ *   - quasi-random points mapped to N(0,1) by Moro's inverse cumulative normal
+ *     (Section III.D);
+ *   - GBM on the Bermudan grid t_k = kT/M, k = 1..M (Sections III.E and V,
+ *     eq. (9), taken as the exact lognormal map built by a Brownian bridge);
+ *   - backward induction over the dates (Section V, eqs. (10)-(11)) with the
+ *     continuation value estimated by least squares over in-the-money paths
+ *     (the regression approach the paper cites as [9], [12], [19]);
+ *   - the discounted mean of eqs. (6)-(8).
+ *
+ * Quasi-random points: unscrambled Sobol (Joe–Kuo direction numbers), Gray
+ * code order, path i uses sequence index i+1; dimension 1 drives W(T) and
+ * dimension q+1 the q-th breadth-first bisection node of the bridge.
+ *
+ * All entry points return AM_OK (0) or a negative error code; on error no
+ * output is written and am_last_error() describes the failure.  Host
+ * pointers are owned by the caller and only read or written during the call.
+ */
+#ifndef AMQMC_H
+#define AMQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Option and model parameters (Section III.C notation in brackets). */
+typedef struct am_params {
+    double S0;              /* spot at t0 [S_0], > 0 */
+    double K;               /* strike [X], > 0 */
+    double r;               /* continuously compounded rate [r], finite */
+    double sigma;           /* volatility [v], > 0 */
+    double T;               /* expiry [T], > 0 */
+    int32_t is_call;        /* 1 call, 0 put */
+    int32_t allow_exercise; /* 1: exercise at t_1..t_{M-1} (least squares) and at
+                               t0 (price = max(h(S0), mean)); 0: European */
+} am_params;
+
+/* Regression basis: functions of x = S/K.  MONOMIAL: 1, x, .., x^d.
+ * LAGUERRE: exp(-x/2) L_n(x), n = 0..d (weighted Laguerre functions).
+ * p = degree + 1 functions, 0 <= degree <= AM_MAX_DEGREE.  The engine solves
+ * in an equivalent basis of the same span (standardised x); fitted values,
+ * and hence prices, do not depend on that choice. */
+typedef struct am_basis {
+    int32_t kind;
+    int32_t degree;
+} am_basis;
+
+enum { AM_BASIS_MONOMIAL = 0, AM_BASIS_LAGUERRE = 1 };
+enum { AM_MAX_DEGREE = 6 };
+
+/* Arithmetic of the bulk path data.
+ *   AM_FP64:      everything binary64.
+ *   AM_FP32_BULK: inverse normal, bridge, paths, basis values and per-thread
+ *                 partial sums in binary32 (blocked, carried in binary64);
+ *                 cross-thread sums, the normal-equation solve, discount
+ *                 factors and the final mean in binary64. */
+enum { AM_FP64 = 0, AM_FP32_BULK = 1 };
+
+enum {
+    AM_OK = 0,
+    AM_EINVAL = -1,      /* a parameter is out of range or not finite */
+    AM_ENOMEM = -2,      /* device or host allocation failed */
+    AM_EDEVICE = -3,     /* a HIP call failed */
+    AM_EDIM = -4,        /* n_dates or n_paths beyond what the engine supports */
+    AM_EWORKSPACE = -5,  /* workspace too small or misaligned */
+    AM_ETIMEOUT = -6     /* a device-side wait exceeded its bound */
+};
+
+/* Price one option, synchronously, on the current HIP device.  Uses a
+ * library-owned stream and workspace (grown on demand, kept per device).
+ * Writes *price and *std_err (naive iid standard error sd(PV)/sqrt(N); 0
+ * when exercise at t0 wins).  Thread-safe; calls on one device serialise. */
+int am_price_american(const am_params *params, int64_t n_paths, int32_t n_dates,
+                      am_basis basis, int32_t dtype, double *price, double *std_err);
+
+/* Workspace bytes am_price_american_ex needs for this shape. */
+size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype);
+
+/* Offsets (bytes from the workspace base) of the regions a test or tool may
+ * read after a call, in this order:
+ *   [0] S: paths, [n_dates][ld] of double (AM_FP64) or float (AM_FP32_BULK),
+ *       row k-1 holds t_k, column i holds path i;
+ *   [1] PV: [ld] per-path cashflow discounted to t0, same type as S;
+ *   [2] per-date records: [n_dates+1][32] double; row k (1 <= k < n_dates)
+ *       holds the date's regression: [0..7] coefficients of the fitted value
+ *       (cashflow discounted to t0) in the engine's standardised basis, [8] 1
+ *       if solved / 0 if the date allowed no exercise, [9] in-the-money count,
+ *       [10..] the moment sums it was solved from;
+ *   [3] result: [8] double {price, std_err, mean_pv, t0_exercise, n_skipped,
+ *       error_flag, 0, 0};
+ *   [4] ld (elements, not bytes); [5] total bytes.
+ * Returns AM_OK or AM_EINVAL. */
+int am_workspace_layout(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype,
+                        size_t out[6]);
+
+/* Price one option asynchronously on `hip_stream` (a hipStream_t; NULL is the
+ * null stream) using the caller's device workspace d_workspace of ws_bytes
+ * (>= am_workspace_bytes, 256-byte aligned, on the current device).  The
+ * workspace must not be shared by calls that may overlap.  If h_out is
+ * non-NULL the call waits for the stream and writes h_out[0] = price,
+ * h_out[1] = std_err; if NULL it returns after enqueueing and the result
+ * stays in the workspace result region. */
+int am_price_american_ex(const am_params *params, int64_t n_paths, int32_t n_dates,
+                         am_basis basis, int32_t dtype, void *d_workspace, size_t ws_bytes,
+                         void *hip_stream, double *h_out);
+
+/* Thread-local description of the last failure on this thread; valid until
+ * the next call on the same thread.  Never NULL. */
+const char *am_last_error(void);
+
+/* Largest n_dates the engine supports (bounded by the Sobol table and the
+ * on-chip generation tables). */
+int am_max_dates(void);
+
+/* Largest n_paths one call supports at this precision on the current device
+ * (paths are kept resident on chip during the backward sweep). */
+int64_t am_max_paths(int32_t dtype);
+
+/* ---------------------------------------------------------------------- */
+/* Inspection entry points used by the parity tests.                       */
+/* ---------------------------------------------------------------------- */
+
+/* Run the generation kernel in a diagnostic mode on the current device and
+ * copy its raw output to host_out ([count_dims][n_paths], row-major):
+ *   what = 1: Sobol integers x_j(i+1) for dims j = 1..n_dims;
+ *   what = 2: inverse-normal values z as double (from the given dtype);
+ *   what = 0: the paths S as double (row k-1 = t_k), for params.
+ * host_out must hold n_dims * n_paths elements (uint32 for what = 1, double
+ * otherwise).  Synchronous. */
+int am_debug_generate(int32_t what, const am_params *params, int64_t n_paths, int32_t n_dims,
+                      int32_t dtype, void *host_out);
+
+/* Host-side bridge schedule for n_dates (no device work): node q in
+ * construction order gets date m[q], Sobol dimension dim[q] (0-based), and
+ * weights so that W(t_m) = wl*W(t_left) + wr*W(t_right) + sd*sqrt(T/M)*z.
+ * Arrays hold n_dates entries. */
+int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left,
+                      int32_t *right, double *wl, double *wr, double *sd);
+
+/* Kernel timing for measurement tools.  While enabled on the calling thread,
+ * each pricing call records HIP events on its stream before the generation
+ * kernel, between the two kernels and after the sweep kernel.
+ * am_profile_read waits for the recorded events and returns the summed
+ * milliseconds of generation (ms[0]) and sweep (ms[1]) and the number of
+ * calls timed since the last read, then clears the record.  Enabling or
+ * disabling also clears it. */
+int am_profile_enable(int32_t on);
+int am_profile_read(double ms[2], int64_t *calls);
+
+/* Test hook: bound the device-side barrier waits of subsequent calls on this
+ * thread to `spins` polls (0 restores the default).  A wait that runs out
+ * makes the call return AM_ETIMEOUT after every workgroup has exited. */
+void am_debug_set_spin_limit(uint32_t spins);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -122,6 +122,8 @@ def _configure(L):
                                   P(ctypes.c_double)]
     L.or_paths.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64, ctypes.c_int,
                            P(ctypes.c_double)]
+    L.or_paths_range.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int, P(ctypes.c_double)]
     L.or_basis_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 P(ctypes.c_double)]
     L.or_lsm_on_paths.argtypes = [P(ctypes.c_double), ctypes.c_int64, ctypes.c_int,
@@ -226,6 +228,18 @@ def paths(S0, K, r, sigma, T, N: int, M: int, is_call=False) -> np.ndarray:
     rc = lib().or_paths(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, _ptr(S, ctypes.c_double))
     if rc != 0:
         raise RuntimeError("or_paths failed")
+    return S
+
+
+def paths_range(S0, K, r, sigma, T, first: int, count: int, M: int) -> np.ndarray:
+    """float64 [M][count]: paths first..first+count-1 (same points as paths())."""
+    p = _params(S0, K, r, sigma, T, False, True)
+    V = directions(M)
+    S = np.zeros((M, count), dtype=np.float64)
+    rc = lib().or_paths_range(ctypes.byref(p), _ptr(V, ctypes.c_uint32), first, count, M,
+                              _ptr(S, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("or_paths_range failed")
     return S
 
 

@@ -199,23 +199,30 @@ void or_bridge_apply(int M, double T, const double *z, double *W)
 /* ------------------------------------------------------------------------ */
 /* GBM paths on the exercise grid (Section V, eq. (9), exact lognormal map). */
 /* ------------------------------------------------------------------------ */
-int or_paths(const or_params *p, const uint32_t *V, int64_t N, int M, double *S)
+/* Paths first..first+count-1 into S[M][count]. */
+int or_paths_range(const or_params *p, const uint32_t *V, int64_t first, int64_t count, int M,
+                   double *S)
 {
     double *z = (double *)malloc(sizeof(double) * (size_t)M);
     double *W = (double *)malloc(sizeof(double) * (size_t)(M + 1));
     if (!z || !W) { free(z); free(W); return -2; }
     double drift = p->r - 0.5 * p->sigma * p->sigma;
-    for (int64_t i = 0; i < N; ++i) {
-        uint64_t n = (uint64_t)i + 1u;                 /* skip the origin */
+    for (int64_t c = 0; c < count; ++c) {
+        uint64_t n = (uint64_t)(first + c) + 1u;       /* skip the origin */
         for (int q = 0; q < M; ++q) z[q] = or_inv_normal_u32(or_sobol_int(V, q, n));
         or_bridge_apply(M, p->T, z, W);
         for (int k = 1; k <= M; ++k) {
             double tk = (double)k * p->T / (double)M;
-            S[(int64_t)(k - 1) * N + i] = p->S0 * exp(drift * tk + p->sigma * W[k]);
+            S[(int64_t)(k - 1) * count + c] = p->S0 * exp(drift * tk + p->sigma * W[k]);
         }
     }
     free(z); free(W);
     return 0;
+}
+
+int or_paths(const or_params *p, const uint32_t *V, int64_t N, int M, double *S)
+{
+    return or_paths_range(p, V, 0, N, M, S);
 }
 
 /* ------------------------------------------------------------------------ */

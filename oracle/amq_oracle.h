@@ -64,6 +64,8 @@ void or_bridge_apply(int M, double T, const double *z, double *W);
 
 /* Paths S[M][N]: row k-1 holds date t_k = kT/M for every path. */
 int or_paths(const or_params *p, const uint32_t *V, int64_t N, int M, double *S);
+int or_paths_range(const or_params *p, const uint32_t *V, int64_t first, int64_t count, int M,
+                   double *S);
 
 /* Basis functions of x = S/K. Returns the number of functions. */
 int or_basis_eval(int kind, int degree, double x, double *psi);

@@ -1,0 +1,266 @@
+"""MI355X quasi-Monte Carlo American option engine — Python binding.
+
+Thin ctypes layer over ``libamqmc.so`` (C-ABI in ``include/amqmc.h``).  Every
+step of the pricing path runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch provides device memory (the workspace) and
+streams for the asynchronous entry point.  Importing the binding never falls
+back to anything else: if the library is missing the calls raise.
+
+Method: Cvetanoska & Stojanovski, "Using High Performance Computing and Monte
+Carlo Simulation for Pricing American Options" (Sections III.D, III.E, V).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamqmc.so")
+
+AM_OK, AM_EINVAL, AM_ENOMEM, AM_EDEVICE, AM_EDIM, AM_EWORKSPACE, AM_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+AM_BASIS_MONOMIAL, AM_BASIS_LAGUERRE = 0, 1
+AM_FP64, AM_FP32_BULK = 0, 1
+AM_MAX_DEGREE = 6
+
+_BASIS_NAMES = {"monomial": AM_BASIS_MONOMIAL, "laguerre": AM_BASIS_LAGUERRE}
+_DTYPE_NAMES = {"fp64": AM_FP64, "f64": AM_FP64, "fp32": AM_FP32_BULK, "fp32_bulk": AM_FP32_BULK,
+                "f32": AM_FP32_BULK}
+
+
+class AmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class am_params(ctypes.Structure):
+    """Option and model parameters (S0, strike K, rate r, volatility sigma, expiry T)."""
+    _fields_ = [("S0", ctypes.c_double), ("K", ctypes.c_double), ("r", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("T", ctypes.c_double),
+                ("is_call", ctypes.c_int32), ("allow_exercise", ctypes.c_int32)]
+
+
+class am_basis(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32)]
+
+
+def make_params(S0, K, r, sigma, T, is_call=False, allow_exercise=True) -> am_params:
+    return am_params(float(S0), float(K), float(r), float(sigma), float(T),
+                     int(bool(is_call)), int(bool(allow_exercise)))
+
+
+def make_basis(kind="monomial", degree=2) -> am_basis:
+    if isinstance(kind, str):
+        kind = _BASIS_NAMES[kind.lower()]
+    return am_basis(int(kind), int(degree))
+
+
+def _dtype(d) -> int:
+    if isinstance(d, str):
+        return _DTYPE_NAMES[d.lower()]
+    return int(d)
+
+
+_lib = None
+
+
+def lib():
+    """Load libamqmc.so; raise (never fall back) if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(or python -m paper_1205_0106_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        i64, i32, sz, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
+        L.am_price_american.argtypes = [P(am_params), i64, i32, am_basis, i32, P(dbl), P(dbl)]
+        L.am_price_american.restype = ctypes.c_int
+        L.am_workspace_bytes.argtypes = [i64, i32, am_basis, i32]
+        L.am_workspace_bytes.restype = sz
+        L.am_workspace_layout.argtypes = [i64, i32, am_basis, i32, P(sz)]
+        L.am_workspace_layout.restype = ctypes.c_int
+        L.am_price_american_ex.argtypes = [P(am_params), i64, i32, am_basis, i32, ctypes.c_void_p,
+                                           sz, ctypes.c_void_p, P(dbl)]
+        L.am_price_american_ex.restype = ctypes.c_int
+        L.am_last_error.argtypes = []
+        L.am_last_error.restype = ctypes.c_char_p
+        L.am_max_dates.argtypes = []
+        L.am_max_dates.restype = ctypes.c_int
+        L.am_max_paths.argtypes = [i32]
+        L.am_max_paths.restype = i64
+        L.am_debug_generate.argtypes = [i32, P(am_params), i64, i32, i32, ctypes.c_void_p]
+        L.am_debug_generate.restype = ctypes.c_int
+        L.am_debug_schedule.argtypes = [i32, P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl), P(dbl)]
+        L.am_debug_schedule.restype = ctypes.c_int
+        L.am_profile_enable.argtypes = [i32]
+        L.am_profile_enable.restype = ctypes.c_int
+        L.am_profile_read.argtypes = [P(dbl), P(i64)]
+        L.am_profile_read.restype = ctypes.c_int
+        L.am_debug_set_spin_limit.argtypes = [ctypes.c_uint32]
+        L.am_debug_set_spin_limit.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != AM_OK:
+        raise AmError(rc, lib().am_last_error().decode())
+
+
+# --------------------------------------------------------------------------
+# C-ABI entry points, same names
+# --------------------------------------------------------------------------
+def am_price_american(params: am_params, n_paths: int, n_dates: int, basis: am_basis,
+                      dtype) -> Tuple[float, float]:
+    """Synchronous pricing with the library-owned workspace and stream."""
+    price, se = ctypes.c_double(), ctypes.c_double()
+    _check(lib().am_price_american(ctypes.byref(params), int(n_paths), int(n_dates), basis,
+                                   _dtype(dtype), ctypes.byref(price), ctypes.byref(se)))
+    return price.value, se.value
+
+
+def am_workspace_bytes(n_paths: int, n_dates: int, basis: am_basis, dtype) -> int:
+    return int(lib().am_workspace_bytes(int(n_paths), int(n_dates), basis, _dtype(dtype)))
+
+
+@dataclass
+class Layout:
+    off_S: int
+    off_PV: int
+    off_rec: int
+    off_result: int
+    ld: int
+    total: int
+
+
+def am_workspace_layout(n_paths: int, n_dates: int, basis: am_basis, dtype) -> Layout:
+    out = (ctypes.c_size_t * 6)()
+    _check(lib().am_workspace_layout(int(n_paths), int(n_dates), basis, _dtype(dtype), out))
+    return Layout(*[int(v) for v in out])
+
+
+def am_price_american_ex(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
+                         workspace, stream=None, wait: bool = True) -> Optional[Tuple[float, float]]:
+    """Asynchronous pricing on a torch CUDA(HIP) stream with a torch workspace.
+
+    ``workspace``: a contiguous uint8 CUDA tensor of >= am_workspace_bytes.
+    ``stream``: torch.cuda.Stream or None (current stream).  With wait=True
+    returns (price, std_err); otherwise returns None and the result stays in
+    the workspace result region."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+    out = (ctypes.c_double * 2)() if wait else None
+    _check(lib().am_price_american_ex(ctypes.byref(params), int(n_paths), int(n_dates), basis,
+                                      _dtype(dtype), ctypes.c_void_p(workspace.data_ptr()),
+                                      workspace.numel(), ctypes.c_void_p(stream.cuda_stream), out))
+    if wait:
+        return out[0], out[1]
+    return None
+
+
+def am_last_error() -> str:
+    return lib().am_last_error().decode()
+
+
+def am_max_dates() -> int:
+    return int(lib().am_max_dates())
+
+
+def am_max_paths(dtype) -> int:
+    return int(lib().am_max_paths(_dtype(dtype)))
+
+
+def am_debug_generate(what: int, params: Optional[am_params], n_paths: int, n_dims: int, dtype):
+    """Diagnostic generation: what=1 Sobol ints [dims][paths] (uint32),
+    what=2 normals, what=0 paths (float64 [dims][paths])."""
+    import numpy as np
+    dt = np.uint32 if what == 1 else np.float64
+    out = np.zeros((n_dims, n_paths), dtype=dt)
+    _check(lib().am_debug_generate(int(what), ctypes.byref(params) if params is not None else None,
+                                   int(n_paths), int(n_dims), _dtype(dtype),
+                                   out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def am_debug_schedule(n_dates: int):
+    import numpy as np
+    m = np.zeros(n_dates, np.int32)
+    dim = np.zeros(n_dates, np.int32)
+    left = np.zeros(n_dates, np.int32)
+    right = np.zeros(n_dates, np.int32)
+    wl = np.zeros(n_dates)
+    wr = np.zeros(n_dates)
+    sd = np.zeros(n_dates)
+    P = ctypes.POINTER
+    _check(lib().am_debug_schedule(int(n_dates), *[a.ctypes.data_as(P(ctypes.c_int32)) for a in (m, dim, left, right)],
+                                   *[a.ctypes.data_as(P(ctypes.c_double)) for a in (wl, wr, sd)]))
+    return dict(m=m, dim=dim, left=left, right=right, wl=wl, wr=wr, sd=sd)
+
+
+def am_profile_enable(on: bool) -> None:
+    _check(lib().am_profile_enable(int(bool(on))))
+
+
+def am_profile_read():
+    """Returns (gen_ms_total, sweep_ms_total, calls) since the last read."""
+    ms = (ctypes.c_double * 2)()
+    n = ctypes.c_int64()
+    _check(lib().am_profile_read(ms, ctypes.byref(n)))
+    return ms[0], ms[1], n.value
+
+
+def am_debug_set_spin_limit(spins: int) -> None:
+    lib().am_debug_set_spin_limit(int(spins))
+
+
+# --------------------------------------------------------------------------
+# Convenience: price with a torch-owned workspace (cached per size)
+# --------------------------------------------------------------------------
+class Pricer:
+    """Holds a torch workspace and stream; prices options through the C-ABI."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream or torch.cuda.Stream(self.device)
+        self.ws = None
+
+    def workspace(self, nbytes: int):
+        import torch
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.ws
+
+    def price(self, params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
+              wait: bool = True):
+        nbytes = am_workspace_bytes(n_paths, n_dates, basis, dtype)
+        ws = self.workspace(nbytes)
+        return am_price_american_ex(params, n_paths, n_dates, basis, dtype, ws, self.stream, wait)
+
+    def views(self, n_paths: int, n_dates: int, basis: am_basis, dtype):
+        """Torch views of the last call's paths, PV, per-date records, result."""
+        import torch
+        lay = am_workspace_layout(n_paths, n_dates, basis, dtype)
+        ws = self.ws
+        el = torch.float64 if _dtype(dtype) == AM_FP64 else torch.float32
+        sz = 8 if el == torch.float64 else 4
+        S = ws[lay.off_S: lay.off_S + n_dates * lay.ld * sz].view(el).view(n_dates, lay.ld)
+        PV = ws[lay.off_PV: lay.off_PV + lay.ld * sz].view(el)
+        rec = ws[lay.off_rec: lay.off_rec + (n_dates + 1) * 32 * 8].view(torch.float64).view(n_dates + 1, 32)
+        res = ws[lay.off_result: lay.off_result + 64].view(torch.float64)
+        return dict(S=S[:, :n_paths], PV=PV[:n_paths], rec=rec, result=res, layout=lay)
+
+
+def price_american(S0, K, r, sigma, T, n_paths, n_dates, *, is_call=False, allow_exercise=True,
+                   basis=("monomial", 2), dtype="fp64") -> Tuple[float, float]:
+    """price_american(params, n_paths, n_dates, basis, dtype) -> (price, stderr)."""
+    p = make_params(S0, K, r, sigma, T, is_call, allow_exercise)
+    b = make_basis(*basis) if isinstance(basis, tuple) else basis
+    return am_price_american(p, n_paths, n_dates, b, dtype)

@@ -1,0 +1,561 @@
+// amq_engine.hip — host engine and C-ABI (include/amqmc.h).
+//
+// Owns per-device state (Sobol direction numbers, bridge schedules per date
+// count, a stream and workspace for the synchronous entry point), validates
+// arguments, lays out the workspace and launches the two kernels.
+#include "amqmc.h"
+#include "amq_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+// Direction numbers V[dim][bit] (uint32), embedded at build time.
+extern "C" const uint32_t amq_sobol_v32[];
+extern "C" const uint32_t amq_sobol_v32_dims;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+thread_local uint32_t g_spin_limit = 0;
+constexpr uint32_t kDefaultSpin = 1u << 22;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(AM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    int64_t ld;
+    size_t s_bytes;  // element size
+    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, total;
+};
+
+Layout make_layout(int64_t N, int32_t M, int32_t dtype)
+{
+    Layout L;
+    L.s_bytes = dtype == AM_FP64 ? 8 : 4;
+    L.ld = (N + amq::kLdAlign - 1) / amq::kLdAlign * amq::kLdAlign;
+    size_t o = 0;
+    L.off_S = o;      o = align256(o + (size_t)M * (size_t)L.ld * L.s_bytes);
+    L.off_PV = o;     o = align256(o + (size_t)L.ld * L.s_bytes);
+    L.off_part = o;   o = align256(o + (size_t)amq::kMaxGroups * amq::kPartStride * 8);
+    L.off_rec = o;    o = align256(o + (size_t)(M + 1) * amq::kRec * 8);
+    L.off_datec = o;  o = align256(o + (size_t)(M + 1) * sizeof(amq::DateConst));
+    L.off_result = o; o = align256(o + 8 * 8 + 16 * 4);   // result[8] then sync[16]
+    L.total = o;
+    return L;
+}
+
+// Depth-first bridge schedule with breadth-first dimension numbering.
+std::vector<amq::BridgeNode> make_schedule(int M)
+{
+    std::vector<int> dim_of(M + 1, -1);
+    std::vector<std::pair<int, int>> q;
+    q.reserve(2 * M + 2);
+    dim_of[M] = 0;
+    int next = 1;
+    q.push_back({0, M});
+    for (size_t h = 0; h < q.size(); ++h) {
+        const int l = q[h].first, r = q[h].second;
+        if (r - l < 2) continue;
+        const int m = (l + r) / 2;
+        dim_of[m] = next++;
+        q.push_back({l, m});
+        q.push_back({m, r});
+    }
+    std::vector<amq::BridgeNode> out;
+    out.reserve(M);
+    auto emit = [&](int m, int l, int r, int sl, int sr, int dst) {
+        amq::BridgeNode n;
+        memset(&n, 0, sizeof n);
+        n.m = m;
+        n.dim = dim_of[m];
+        n.sl = sl; n.sr = sr; n.dst = dst;
+        n.fm = (float)m;
+        if (l == 0 && r == 0) {           // root: W(t_M) = sqrt(M) z in sqrt(dt) units
+            n.wl = 0.0; n.wr = 0.0; n.sd = sqrt((double)M);
+        } else {
+            const double span = (double)(r - l);
+            n.wl = (double)(r - m) / span;
+            n.wr = (double)(m - l) / span;
+            n.sd = sqrt((double)(m - l) * (double)(r - m) / span);
+        }
+        n.fwl = (float)n.wl; n.fwr = (float)n.wr; n.fsd = (float)n.sd;
+        out.push_back(n);
+    };
+    emit(M, 0, 0, 0, 0, 1);
+    // explicit stack: (l, r, slot of W(l), slot of W(r), depth of the midpoint)
+    struct Fr { int l, r, sl, sr, depth; };
+    std::vector<Fr> st;
+    st.push_back({0, M, 0, 1, 1});
+    while (!st.empty()) {
+        Fr f = st.back();
+        st.pop_back();
+        if (f.r - f.l < 2) continue;
+        const int m = (f.l + f.r) / 2;
+        const int dst = f.depth + 1;
+        emit(m, f.l, f.r, f.sl, f.sr, dst);
+        st.push_back({m, f.r, dst, f.sr, f.depth + 1});   // right after left
+        st.push_back({f.l, m, f.sl, dst, f.depth + 1});
+    }
+    return out;
+}
+
+int max_slot(const std::vector<amq::BridgeNode> &s)
+{
+    int mx = 0;
+    for (auto &n : s) mx = n.dst > mx ? n.dst : mx;
+    return mx;
+}
+
+struct Plan { int ppt; int G; };
+
+struct DevState {
+    int dev = -1;
+    int num_cu = 0;
+    uint32_t *d_V = nullptr;
+    int vdims = 0;
+    std::mutex mu;                                  // schedule and occupancy maps
+    std::map<int, amq::BridgeNode *> sched;
+    std::mutex sync_mu;                             // synchronous entry point's workspace
+    hipStream_t stream = nullptr;                   // synchronous entry point
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::map<long, int> occ;                        // (fp64, ppt, degree) -> groups per CU
+};
+
+std::mutex g_dev_mu;
+std::map<int, std::unique_ptr<DevState>> g_devs;
+
+int get_state(DevState **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_devs.find(dev);
+    if (it != g_devs.end()) { *out = it->second.get(); return AM_OK; }
+    std::unique_ptr<DevState> st(new DevState);
+    st->dev = dev;
+    HIP_TRY(hipDeviceGetAttribute(&st->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int coop = 0;
+    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return fail(AM_EDEVICE, "device %d does not support cooperative launches", dev);
+    st->vdims = (int)amq_sobol_v32_dims < amq::kMaxDates ? (int)amq_sobol_v32_dims : amq::kMaxDates;
+    const size_t vb = (size_t)st->vdims * 32 * sizeof(uint32_t);
+    if (hipMalloc((void **)&st->d_V, vb) != hipSuccess)
+        return fail(AM_ENOMEM, "hipMalloc of %zu bytes (direction numbers) failed", vb);
+    HIP_TRY(hipMemcpy(st->d_V, amq_sobol_v32, vb, hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking));
+    *out = st.get();
+    g_devs[dev] = std::move(st);
+    return AM_OK;
+}
+
+int get_schedule(DevState *st, int M, const amq::BridgeNode **out)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    auto it = st->sched.find(M);
+    if (it != st->sched.end()) { *out = it->second; return AM_OK; }
+    std::vector<amq::BridgeNode> h = make_schedule(M);
+    if ((int)h.size() != M || max_slot(h) >= amq::kMaxSlots)
+        return fail(AM_EDIM, "bridge schedule for %d dates does not fit the register window", M);
+    amq::BridgeNode *d = nullptr;
+    const size_t b = sizeof(amq::BridgeNode) * (size_t)M;
+    if (hipMalloc((void **)&d, b) != hipSuccess) return fail(AM_ENOMEM, "hipMalloc of bridge schedule failed");
+    HIP_TRY(hipMemcpy(d, h.data(), b, hipMemcpyHostToDevice));
+    st->sched[M] = d;
+    *out = d;
+    return AM_OK;
+}
+
+int groups_per_cu(DevState *st, int fp64, int ppt, int degree)
+{
+    const long key = ((long)fp64 << 20) | ((long)ppt << 4) | degree;
+    std::lock_guard<std::mutex> lk(st->mu);
+    auto it = st->occ.find(key);
+    if (it != st->occ.end()) return it->second;
+    const int nb = amq::sweep_blocks_per_cu(fp64, ppt, degree);
+    st->occ[key] = nb;
+    return nb;
+}
+
+const int kPPT32[] = {4, 16, 64, 128};
+const int kPPT64[] = {2, 8, 32, 64};
+
+int choose_plan(DevState *st, int64_t N, int fp64, int degree, Plan *p)
+{
+    const int *ppts = fp64 ? kPPT64 : kPPT32;
+    const int n = 4;
+    for (int i = 0; i < n; ++i) {
+        const int ppt = ppts[i];
+        const int per_cu = groups_per_cu(st, fp64, ppt, degree);
+        if (per_cu <= 0) continue;
+        int64_t gmax = (int64_t)per_cu * st->num_cu;
+        if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
+        const int64_t G = (N + (int64_t)amq::kWG * ppt - 1) / ((int64_t)amq::kWG * ppt);
+        if (G <= gmax) { p->ppt = ppt; p->G = (int)G; return AM_OK; }
+    }
+    return fail(AM_EDIM, "n_paths = %lld exceeds what one resident sweep holds on this device",
+                (long long)N);
+}
+
+int validate(const am_params *p, int64_t N, int32_t M, am_basis b, int32_t dtype)
+{
+    if (!p) return fail(AM_EINVAL, "params is NULL");
+    const double v[] = {p->S0, p->K, p->sigma, p->T};
+    const char *nm[] = {"S0", "K", "sigma", "T"};
+    for (int i = 0; i < 4; ++i)
+        if (!(isfinite(v[i]) && v[i] > 0.0)) return fail(AM_EINVAL, "%s must be finite and > 0", nm[i]);
+    if (!isfinite(p->r)) return fail(AM_EINVAL, "r must be finite");
+    if (p->is_call != 0 && p->is_call != 1) return fail(AM_EINVAL, "is_call must be 0 or 1");
+    if (p->allow_exercise != 0 && p->allow_exercise != 1) return fail(AM_EINVAL, "allow_exercise must be 0 or 1");
+    if (b.kind != AM_BASIS_MONOMIAL && b.kind != AM_BASIS_LAGUERRE) return fail(AM_EINVAL, "unknown basis kind %d", b.kind);
+    if (b.degree < 0 || b.degree > AM_MAX_DEGREE) return fail(AM_EINVAL, "basis degree %d outside [0, %d]", b.degree, AM_MAX_DEGREE);
+    if (dtype != AM_FP64 && dtype != AM_FP32_BULK) return fail(AM_EINVAL, "unknown dtype %d", dtype);
+    if (M < 1) return fail(AM_EINVAL, "n_dates must be >= 1");
+    if (M > amq::kMaxDates || (uint32_t)M > amq_sobol_v32_dims)
+        return fail(AM_EDIM, "n_dates = %d exceeds %d", M, amq::kMaxDates);
+    if (N < (int64_t)b.degree + 2) return fail(AM_EINVAL, "n_paths must be >= degree + 2");
+    if (N > 0xFFFFFFFFll) return fail(AM_EDIM, "n_paths beyond the 32-bit Sobol index range");
+    const double sd = p->sigma * sqrt(p->T);
+    if (!(sd > 1e-12) || !isfinite(p->r * p->T)) return fail(AM_EINVAL, "degenerate sigma*sqrt(T) or r*T");
+    return AM_OK;
+}
+
+// Per-thread kernel timing (am_profile_*): three events per timed call.
+struct ProfRec { hipEvent_t e[3]; };
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> pool;   // created events, reused
+    size_t used = 0;
+};
+thread_local Profiler g_prof;
+
+int prof_slot(ProfRec **out)
+{
+    if (g_prof.used == g_prof.pool.size()) {
+        ProfRec r;
+        for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&r.e[i]));
+        g_prof.pool.push_back(r);
+    }
+    *out = &g_prof.pool[g_prof.used++];
+    return AM_OK;
+}
+
+// Enqueue both kernels; result stays in the workspace.
+int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, int32_t dtype,
+            char *ws, const Layout &L, hipStream_t stream)
+{
+    const int fp64 = dtype == AM_FP64;
+    Plan plan;
+    int rc = choose_plan(st, N, fp64, b.degree, &plan);
+    if (rc) return rc;
+    const amq::BridgeNode *sched = nullptr;
+    rc = get_schedule(st, M, &sched);
+    if (rc) return rc;
+
+    amq::GenArgs ga;
+    memset(&ga, 0, sizeof ga);
+    ga.S = ws + L.off_S;
+    ga.V = st->d_V;
+    ga.sched = sched;
+    ga.datec = (amq::DateConst *)(ws + L.off_datec);
+    ga.sync = (uint32_t *)(ws + L.off_result + 64);
+    ga.N = N; ga.ld = L.ld;
+    ga.nblocks = L.ld / 64;
+    ga.M = M;
+    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
+    ga.R = (int32_t)(R < 1 ? 1 : R);
+    ga.what = 0;
+    ga.S0 = p->S0; ga.K = p->K; ga.r = p->r; ga.sigma = p->sigma; ga.T = p->T;
+    const double dt = p->T / (double)M;
+    ga.mu = (p->r - 0.5 * p->sigma * p->sigma) * dt;
+    ga.vol = p->sigma * sqrt(dt);
+    ProfRec *pr = nullptr;
+    if (g_prof.on) {
+        int prc = prof_slot(&pr);
+        if (prc) return prc;
+        HIP_TRY(hipEventRecord(pr->e[0], stream));
+    }
+    HIP_TRY(amq::launch_generate(ga, fp64, stream));
+    if (pr) HIP_TRY(hipEventRecord(pr->e[1], stream));
+
+    amq::SweepArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.S = ws + L.off_S;
+    sa.pv_out = ws + L.off_PV;
+    sa.part = (double *)(ws + L.off_part);
+    sa.rec = (double *)(ws + L.off_rec);
+    sa.result = (double *)(ws + L.off_result);
+    sa.sync = (uint32_t *)(ws + L.off_result + 64);
+    sa.datec = (const amq::DateConst *)(ws + L.off_datec);
+    sa.N = N; sa.ld = L.ld;
+    sa.M = M; sa.G = plan.G;
+    sa.is_call = p->is_call; sa.allow_exercise = p->allow_exercise;
+    sa.laguerre = b.kind == AM_BASIS_LAGUERRE; sa.degree = b.degree;
+    sa.S0 = p->S0; sa.K = p->K;
+    sa.spin_limit = g_spin_limit ? g_spin_limit : kDefaultSpin;
+    hipError_t e = amq::launch_sweep(sa, fp64, plan.ppt, stream);
+    if (e != hipSuccess)
+        return fail(AM_EDEVICE, "sweep launch (ppt %d, groups %d) failed: %s", plan.ppt, plan.G,
+                    hipGetErrorString(e));
+    if (pr) HIP_TRY(hipEventRecord(pr->e[2], stream));
+    return AM_OK;
+}
+
+thread_local double *g_pinned = nullptr;
+
+int fetch_result(char *ws, const Layout &L, hipStream_t stream, double *h_out)
+{
+    if (!g_pinned) {
+        if (hipHostMalloc((void **)&g_pinned, 256, hipHostMallocDefault) != hipSuccess) {
+            g_pinned = nullptr;
+            return fail(AM_ENOMEM, "hipHostMalloc of the result buffer failed");
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(g_pinned, ws + L.off_result, 128, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const uint32_t *sync = (const uint32_t *)((const char *)g_pinned + 64);
+    if (sync[2] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
+    if (!isfinite(g_pinned[0]) || !isfinite(g_pinned[1]))
+        return fail(AM_EDEVICE, "non-finite result");
+    h_out[0] = g_pinned[0];
+    h_out[1] = g_pinned[1];
+    return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *am_last_error(void) { return g_err.c_str(); }
+
+int am_max_dates(void)
+{
+    return (int)amq_sobol_v32_dims < amq::kMaxDates ? (int)amq_sobol_v32_dims : amq::kMaxDates;
+}
+
+int64_t am_max_paths(int32_t dtype)
+{
+    DevState *st = nullptr;
+    if (get_state(&st)) return 0;
+    const int fp64 = dtype == AM_FP64;
+    const int *ppts = fp64 ? kPPT64 : kPPT32;
+    const int n = 4;
+    int64_t best = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t worst = -1;
+        for (int d = 0; d <= AM_MAX_DEGREE; ++d) {
+            int64_t g = (int64_t)groups_per_cu(st, fp64, ppts[i], d) * st->num_cu;
+            if (g > amq::kMaxGroups) g = amq::kMaxGroups;
+            const int64_t cap = g * amq::kWG * ppts[i];
+            worst = worst < 0 || cap < worst ? cap : worst;
+        }
+        best = worst > best ? worst : best;
+    }
+    return best;
+}
+
+size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype)
+{
+    (void)basis;
+    if (n_paths < 1 || n_dates < 1) return 0;
+    return make_layout(n_paths, n_dates, dtype).total;
+}
+
+int am_workspace_layout(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype, size_t out[6])
+{
+    (void)basis;
+    if (!out || n_paths < 1 || n_dates < 1 || (dtype != AM_FP64 && dtype != AM_FP32_BULK))
+        return fail(AM_EINVAL, "bad arguments to am_workspace_layout");
+    Layout L = make_layout(n_paths, n_dates, dtype);
+    out[0] = L.off_S; out[1] = L.off_PV; out[2] = L.off_rec; out[3] = L.off_result;
+    out[4] = (size_t)L.ld; out[5] = L.total;
+    return AM_OK;
+}
+
+int am_price_american_ex(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                         int32_t dtype, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                         double *h_out)
+{
+    int rc = validate(params, n_paths, n_dates, basis, dtype);
+    if (rc) return rc;
+    Layout L = make_layout(n_paths, n_dates, dtype);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", L.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    rc = enqueue(st, params, n_paths, n_dates, basis, dtype, (char *)d_workspace, L, stream);
+    if (rc) return rc;
+    if (!h_out) return AM_OK;
+    return fetch_result((char *)d_workspace, L, stream, h_out);
+}
+
+int am_price_american(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                      int32_t dtype, double *price, double *std_err)
+{
+    if (!price || !std_err) return fail(AM_EINVAL, "price and std_err must be non-NULL");
+    int rc = validate(params, n_paths, n_dates, basis, dtype);
+    if (rc) return rc;
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    Layout L = make_layout(n_paths, n_dates, dtype);
+    std::lock_guard<std::mutex> lk(st->sync_mu);
+    if (st->ws_bytes < L.total) {
+        if (st->ws) { HIP_TRY(hipStreamSynchronize(st->stream)); HIP_TRY(hipFree(st->ws)); }
+        st->ws = nullptr;
+        st->ws_bytes = 0;
+        if (hipMalloc(&st->ws, L.total) != hipSuccess)
+            return fail(AM_ENOMEM, "hipMalloc of %zu workspace bytes failed", L.total);
+        st->ws_bytes = L.total;
+    }
+    rc = enqueue(st, params, n_paths, n_dates, basis, dtype, (char *)st->ws, L, st->stream);
+    double out[2] = {0.0, 0.0};
+    if (!rc) rc = fetch_result((char *)st->ws, L, st->stream, out);
+    if (rc) return rc;
+    *price = out[0];
+    *std_err = out[1];
+    return AM_OK;
+}
+
+int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left, int32_t *right,
+                      double *wl, double *wr, double *sd)
+{
+    if (n_dates < 1 || n_dates > amq::kMaxDates) return fail(AM_EDIM, "n_dates out of range");
+    std::vector<amq::BridgeNode> s = make_schedule(n_dates);
+    // recover left/right dates from slots: replay the slot contents
+    std::vector<int> slot_date(amq::kMaxSlots + 1, 0);
+    for (int q = 0; q < n_dates; ++q) {
+        const amq::BridgeNode &n = s[q];
+        if (m) m[q] = n.m;
+        if (dim) dim[q] = n.dim;
+        if (left) left[q] = slot_date[n.sl];
+        if (right) right[q] = n.sr == 0 && q == 0 ? 0 : slot_date[n.sr];
+        if (wl) wl[q] = n.wl;
+        if (wr) wr[q] = n.wr;
+        if (sd) sd[q] = n.sd;
+        if (n.dst <= amq::kMaxSlots) slot_date[n.dst] = n.m;
+    }
+    return AM_OK;
+}
+
+void am_debug_set_spin_limit(uint32_t spins) { g_spin_limit = spins; }
+
+int am_profile_enable(int32_t on)
+{
+    g_prof.on = on != 0;
+    g_prof.used = 0;
+    return AM_OK;
+}
+
+int am_profile_read(double ms[2], int64_t *calls)
+{
+    if (!ms || !calls) return fail(AM_EINVAL, "ms and calls must be non-NULL");
+    double g = 0.0, w = 0.0;
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        ProfRec &r = g_prof.pool[i];
+        HIP_TRY(hipEventSynchronize(r.e[2]));
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, r.e[0], r.e[1]));
+        HIP_TRY(hipEventElapsedTime(&b, r.e[1], r.e[2]));
+        g += a;
+        w += b;
+    }
+    ms[0] = g;
+    ms[1] = w;
+    *calls = (int64_t)g_prof.used;
+    g_prof.used = 0;
+    return AM_OK;
+}
+
+int am_debug_generate(int32_t what, const am_params *params, int64_t n_paths, int32_t n_dims,
+                      int32_t dtype, void *host_out)
+{
+    if (!host_out) return fail(AM_EINVAL, "host_out is NULL");
+    if (what < 0 || what > 2) return fail(AM_EINVAL, "what must be 0, 1 or 2");
+    am_basis b = {AM_BASIS_MONOMIAL, 0};
+    am_params dflt = {100.0, 100.0, 0.0, 0.2, 1.0, 0, 0};
+    const am_params *p = params ? params : &dflt;
+    int rc = validate(p, n_paths, n_dims, b, dtype);
+    if (rc) return rc;
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    const amq::BridgeNode *sched = nullptr;
+    rc = get_schedule(st, n_dims, &sched);
+    if (rc) return rc;
+    const int fp64 = dtype == AM_FP64;
+    const int64_t ld = (n_paths + 63) / 64 * 64;
+    const size_t el = what == 1 ? 4 : (what == 2 ? 8 : (fp64 ? 8 : 4));
+    const size_t out_b = (size_t)n_dims * ld * el;
+    const size_t aux_b = align256((size_t)(n_dims + 1) * sizeof(amq::DateConst)) + 256;
+    char *d = nullptr;
+    if (hipMalloc((void **)&d, align256(out_b) + aux_b) != hipSuccess)
+        return fail(AM_ENOMEM, "hipMalloc for the diagnostic output failed");
+    amq::GenArgs ga;
+    memset(&ga, 0, sizeof ga);
+    ga.S = d;
+    ga.V = st->d_V;
+    ga.sched = sched;
+    ga.datec = (amq::DateConst *)(d + align256(out_b));
+    ga.sync = (uint32_t *)(d + align256(out_b) + align256((size_t)(n_dims + 1) * sizeof(amq::DateConst)));
+    ga.N = n_paths; ga.ld = ld; ga.nblocks = (n_paths + 63) / 64; ga.M = n_dims;
+    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
+    ga.R = (int32_t)(R < 1 ? 1 : R);
+    ga.what = what;
+    ga.S0 = p->S0; ga.K = p->K; ga.r = p->r; ga.sigma = p->sigma; ga.T = p->T;
+    const double dt = p->T / (double)n_dims;
+    ga.mu = (p->r - 0.5 * p->sigma * p->sigma) * dt;
+    ga.vol = p->sigma * sqrt(dt);
+    hipError_t e = amq::launch_generate(ga, fp64, st->stream);
+    std::vector<char> h(out_b);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, out_b, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(AM_EDEVICE, "diagnostic generation failed: %s", hipGetErrorString(e));
+    // compact [dims][ld] -> [dims][n_paths]; paths as double
+    for (int32_t j = 0; j < n_dims; ++j) {
+        const char *src = h.data() + (size_t)j * ld * el;
+        if (what == 1) {
+            memcpy((uint32_t *)host_out + (size_t)j * n_paths, src, (size_t)n_paths * 4);
+        } else if (el == 8) {
+            memcpy((double *)host_out + (size_t)j * n_paths, src, (size_t)n_paths * 8);
+        } else {
+            const float *f = (const float *)src;
+            double *o = (double *)host_out + (size_t)j * n_paths;
+            for (int64_t i = 0; i < n_paths; ++i) o[i] = (double)f[i];
+        }
+    }
+    return AM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// amq_internal.h — types shared by the HIP kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amq {
+
+constexpr int kWG = 256;          // threads per workgroup (4 wave64)
+constexpr int kWaves = kWG / 64;
+constexpr int kMaxSlots = 20;     // bridge register window (tree depth + 2)
+constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS) bound this
+constexpr int kRec = 32;          // doubles per date record
+constexpr int kPartStride = 32;   // doubles per workgroup partial-sum slot
+constexpr int kMaxGroups = 2048;  // partial-sum slots in the workspace
+constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
+
+// One node of the Brownian bridge, in depth-first construction order.  The
+// value of W at date m (in units of sqrt(dt)) is
+//   W[dst] = wl * W[sl] + wr * W[sr] + sd * z(dim)
+// where slots hold the values of the current node's ancestors (slot 0 is the
+// constant W(0) = 0).  Both precisions are stored so each kernel reads one.
+struct alignas(64) BridgeNode {
+    int32_t m;      // date index 1..M
+    int32_t dim;    // Sobol dimension, 0-based
+    int32_t sl, sr, dst;
+    float fm;       // m as float
+    double wl, wr, sd;
+    float fwl, fwr, fsd;
+    int32_t pad;
+};
+static_assert(sizeof(BridgeNode) == 64, "bridge node is one scalar cache line");
+
+// Per-date constants written by the generation kernel, read by the sweep.
+//   disc = exp(-r t_k); standardised abscissa xs = S * xa + xb with
+//   xa = 1/(K sd_k), xb = -mean_k/sd_k (mean/sd of S_k/K under the model).
+struct DateConst {
+    double disc, xa, xb, pad;
+};
+
+struct GenArgs {
+    void *S;                  // [M][ld] T (what = 0) or debug output
+    const uint32_t *V;        // [dims][32] direction numbers
+    const BridgeNode *sched;  // [M]
+    DateConst *datec;         // [M+1]
+    uint32_t *sync;           // barrier words, zeroed here
+    int64_t N, ld;
+    int64_t nblocks;          // 64-path blocks to write: ld / 64 (padding included)
+    int32_t M, R;             // dates, 64-path blocks per wave
+    int32_t what;             // 0 paths, 1 sobol ints, 2 normals (debug)
+    int32_t pad;
+    double S0, K, r, sigma, T;
+    double mu, vol;           // (r - sigma^2/2) dt, sigma sqrt(dt)
+};
+
+struct SweepArgs {
+    const void *S;            // [M][ld] T
+    void *pv_out;             // [ld] T
+    double *part;             // [kMaxGroups][kPartStride]
+    double *rec;              // [M+1][kRec]
+    double *result;           // [8]
+    uint32_t *sync;           // [0] arrivals, [1] released epoch, [2] error
+    const DateConst *datec;   // [M+1]
+    int64_t N, ld;
+    int32_t M, G;
+    int32_t is_call, allow_exercise, laguerre, degree;
+    double S0, K;
+    uint32_t spin_limit;
+    int32_t pad;
+};
+
+// Launchers (defined with the kernels).
+hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s);
+// Returns hipErrorInvalidValue if no kernel exists for (fp64, ppt, degree).
+hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s);
+// Workgroups of the sweep kernel that fit on one CU for (fp64, ppt, degree).
+int sweep_blocks_per_cu(int fp64, int ppt, int degree);
+size_t generate_lds_bytes(int M);
+
+}  // namespace amq

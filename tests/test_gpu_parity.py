@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle on identical points.
+
+Every call goes through the C-ABI (paper_1205_0106_amd binding).  Integer
+work (Sobol points, in-the-money counts) must match bit for bit; prices within
+1e-4 absolute in FP64 mode and 2e-3 in FP32-bulk mode; per-path values to the
+tolerance their arithmetic allows.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1205_0106_amd.workloads import CONFIG1, CONFIG2, CONFIG4
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"fp64": 1e-4, "fp32": 2e-3}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def amq():
+    import torch
+    import paper_1205_0106_amd as amq
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    amq.lib()
+    return amq
+
+
+@pytest.fixture(scope="module")
+def pricer(amq):
+    return amq.Pricer(0)
+
+
+def _kind(orc, name):
+    return orc.LAGUERRE if name == "laguerre" else orc.MONOMIAL
+
+
+def gpu_price(amq, pricer, w=None, *, N=None, M=None, dtype="fp64", basis=None, is_call=None,
+              allow_exercise=None, **over):
+    kw = dict(w.params()) if w is not None else {}
+    kw.update(over)
+    N = N if N is not None else w.n_paths
+    M = M if M is not None else w.n_dates
+    basis = basis if basis is not None else w.basis
+    is_call = is_call if is_call is not None else (w.is_call if w is not None else False)
+    allow_exercise = allow_exercise if allow_exercise is not None else \
+        (w.allow_exercise if w is not None else True)
+    p = amq.make_params(kw["S0"], kw["K"], kw["r"], kw["sigma"], kw["T"], is_call, allow_exercise)
+    b = amq.make_basis(*basis)
+    log(f"  gpu: N={N} M={M} dtype={dtype} basis={basis} call={is_call} ex={allow_exercise} {kw}")
+    price, se = pricer.price(p, N, M, b, dtype)
+    v = pricer.views(N, M, b, dtype)
+    return price, se, v
+
+
+def oracle_price(orc, w=None, *, N=None, M=None, basis=None, is_call=None, allow_exercise=None, **over):
+    kw = dict(w.params()) if w is not None else {}
+    kw.update(over)
+    N = N if N is not None else w.n_paths
+    M = M if M is not None else w.n_dates
+    basis = basis if basis is not None else w.basis
+    is_call = is_call if is_call is not None else (w.is_call if w is not None else False)
+    allow_exercise = allow_exercise if allow_exercise is not None else \
+        (w.allow_exercise if w is not None else True)
+    return orc.price_american(**kw, N=N, M=M, is_call=is_call, allow_exercise=allow_exercise,
+                              kind=_kind(orc, basis[0]), degree=basis[1], detail=True)
+
+
+# --------------------------------------------------------------------------
+# Generation: Sobol integers, inverse normal, paths
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dims,N", [(1, 100), (50, 16384), (100, 4097), (252, 3000), (365, 1000),
+                                    (7, 64 * 33 + 5)])
+def test_sobol_integers_bit_exact(amq, orc, dims, N):
+    log(f"sobol dims={dims} N={N}")
+    got = amq.am_debug_generate(1, None, N, dims, "fp32")
+    want = orc.sobol_block(dims, 1, N).T          # path i uses index i + 1
+    assert np.array_equal(got, want)
+
+
+def test_sobol_integers_large_index(amq, orc):
+    # enough paths that waves walk many 64-point blocks (Gray-code carries)
+    N, dims = 1 << 18, 3
+    got = amq.am_debug_generate(1, None, N, dims, "fp32")
+    for first in (0, 4095, 65535, 131071, N - 300):
+        want = orc.sobol_block(dims, first + 1, 300).T
+        assert np.array_equal(got[:, first:first + 300], want)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_inverse_normal(amq, orc, dtype):
+    N, dims = 4096, 20
+    z = amq.am_debug_generate(2, None, N, dims, dtype)
+    x = orc.sobol_block(dims, 1, N).T
+    want = np.vectorize(orc.inv_normal_u32)(x)
+    err = np.abs(z - want)
+    log(f"  max |z - oracle| ({dtype}) = {err.max():.3e}")
+    if dtype == "fp64":
+        assert err.max() <= 1e-13 * np.abs(want).max()
+    else:
+        assert np.all(err <= 2e-6 + 2e-6 * np.abs(want))
+
+
+@pytest.mark.parametrize("dtype,rtol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("M", [1, 2, 3, 17, 50])
+def test_paths_match_oracle(amq, orc, dtype, rtol, M):
+    N = 1000
+    p = amq.make_params(36.0, 40.0, 0.06, 0.2, 1.0)
+    got = amq.am_debug_generate(0, p, N, M, dtype)
+    want = orc.paths(36.0, 40.0, 0.06, 0.2, 1.0, N, M)
+    rel = np.abs(got - want) / want
+    log(f"  paths M={M} {dtype}: max rel err {rel.max():.3e}")
+    assert rel.max() <= rtol
+
+
+# --------------------------------------------------------------------------
+# Prices on the configurations
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_config1_price_and_paths(amq, orc, pricer, dtype):
+    w = CONFIG1
+    price, se, v = gpu_price(amq, pricer, w, dtype=dtype)
+    ores, od = oracle_price(orc, w)
+    err = abs(price - ores.price)
+    log(f"config1 {dtype}: gpu {price:.10f} oracle {ores.price:.10f} |err| {err:.3e} se {se:.4e}")
+    assert err <= TOL[dtype]
+    assert abs(se - ores.std_err) <= 0.02 * ores.std_err
+    S = v["S"].cpu().numpy().astype(np.float64)
+    want = orc.paths(**w.params(), N=w.n_paths, M=w.n_dates)
+    assert np.abs(S - want).max() / want.max() <= (1e-12 if dtype == "fp64" else 2e-5)
+    rec = v["rec"].cpu().numpy()
+    nitm = rec[1:w.n_dates, 9].astype(np.int64)
+    diff = np.abs(nitm - od["nitm"][1:w.n_dates])
+    if dtype == "fp64":
+        assert diff.max() == 0
+    else:
+        assert diff.max() <= 3
+    pv = v["PV"].cpu().numpy().astype(np.float64)
+    bad = np.abs(pv - od["pv"]) > (1e-10 if dtype == "fp64" else 1e-4) * np.maximum(1.0, od["pv"])
+    log(f"  per-path PV mismatches: {bad.sum()} of {w.n_paths}")
+    assert bad.mean() <= (1e-3 if dtype == "fp64" else 2e-2)
+
+
+@pytest.fixture(scope="module")
+def config2_oracle(orc):
+    path = os.path.join(GOLDEN, "oracle_config2.json")
+    if os.path.exists(path):
+        return json.load(open(path))
+    res, d = oracle_price(orc, CONFIG2)
+    return dict(price=res.price, std_err=res.std_err, n_itm=[int(v) for v in d["nitm"]])
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_config2_full_size(amq, orc, pricer, config2_oracle, dtype):
+    w = CONFIG2
+    price, se, v = gpu_price(amq, pricer, w, dtype=dtype)
+    err = abs(price - config2_oracle["price"])
+    log(f"config2 {dtype}: gpu {price:.10f} oracle {config2_oracle['price']:.10f} |err| {err:.3e}")
+    assert err <= TOL[dtype]
+    rec = v["rec"].cpu().numpy()
+    nitm = rec[1:w.n_dates, 9].astype(np.int64)
+    diff = np.abs(nitm - np.array(config2_oracle["n_itm"][1:w.n_dates]))
+    assert diff.max() <= (0 if dtype == "fp64" else 8)
+    # sampled paths, computed one by one by the oracle
+    S = v["S"]
+    for first in (0, 123457, w.n_paths - 257):
+        want = orc.paths_range(**w.params(), first=first, count=257, M=w.n_dates)
+        got = S[:, first:first + 257].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() / want.max() <= (1e-12 if dtype == "fp64" else 2e-5)
+
+
+def test_config4_full_size_fp32(amq, orc, pricer):
+    path = os.path.join(GOLDEN, "oracle_config4.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle_config4.json not generated (tests/golden/make_oracle_goldens.py 4)")
+    g = json.load(open(path))
+    w = CONFIG4
+    price, se, v = gpu_price(amq, pricer, w, dtype="fp32")
+    err = abs(price - g["price"])
+    log(f"config4 fp32: gpu {price:.10f} oracle {g['price']:.10f} |err| {err:.3e}")
+    assert err <= TOL["fp32"]
+    S = v["S"]
+    for first in (0, (1 << 23) + 77, w.n_paths - 129):
+        want = orc.paths_range(**w.params(), first=first, count=129, M=w.n_dates)
+        got = S[:, first:first + 129].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() / want.max() <= 2e-5
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,M", [(4, 3), (10, 1), (63, 2), (64, 5), (65, 7), (1000, 17),
+                                 (4097, 12), (33001, 9), (70000, 3)])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
+    kw = dict(S0=100.0, K=105.0, r=0.04, sigma=0.25, T=0.75)
+    price, se, v = gpu_price(amq, pricer, None, N=N, M=M, dtype=dtype, basis=("monomial", 2), **kw)
+    ores, od = oracle_price(orc, None, N=N, M=M, basis=("monomial", 2), **kw)
+    log(f"  N={N} M={M} {dtype}: gpu {price:.10f} oracle {ores.price:.10f}")
+    if dtype == "fp64" or N >= 1000:
+        assert abs(price - ores.price) <= TOL[dtype]
+    else:
+        # a handful of paths: FP32 rounding can move a whole regression; check level only
+        assert abs(price - ores.price) <= 0.02 * ores.price + TOL[dtype]
+
+
+@pytest.mark.parametrize("call", [False, True])
+@pytest.mark.parametrize("basis", [("monomial", 1), ("monomial", 3), ("laguerre", 2), ("laguerre", 4),
+                                   ("monomial", 6), ("monomial", 0)])
+def test_bases_and_calls_fp64(amq, orc, pricer, call, basis):
+    kw = dict(S0=100.0, K=100.0, r=0.05, sigma=0.3, T=1.0)
+    price, se, v = gpu_price(amq, pricer, None, N=1 << 15, M=20, basis=basis, is_call=call, **kw)
+    ores, od = oracle_price(orc, None, N=1 << 15, M=20, basis=basis, is_call=call, **kw)
+    log(f"  {basis} call={call}: gpu {price:.10f} oracle {ores.price:.10f}")
+    assert abs(price - ores.price) <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_european_mode(amq, orc, pricer, dtype):
+    for call in (False, True):
+        price, se, _ = gpu_price(amq, pricer, CONFIG1, dtype=dtype, is_call=call, allow_exercise=False)
+        ores, _ = oracle_price(orc, CONFIG1, is_call=call, allow_exercise=False)
+        assert abs(price - ores.price) <= TOL[dtype]
+        bs = orc.bs_price(**CONFIG1.params(), is_call=call)
+        assert abs(price - bs) < 0.01
+
+
+def test_t0_exercise_wins(amq, orc, pricer):
+    kw = dict(S0=40.0, K=100.0, r=0.08, sigma=0.1, T=1.0)
+    price, se, v = gpu_price(amq, pricer, None, N=4096, M=10, **kw)
+    ores, _ = oracle_price(orc, None, N=4096, M=10, basis=("monomial", 2), **kw)
+    assert ores.t0_exercise and price == 60.0 and se == 0.0
+    assert v["result"].cpu().numpy()[3] == 1.0
+
+
+def test_degenerate_dates_skip_exercise(amq, orc, pricer):
+    # deep out of the money: most dates have fewer in-the-money paths than p
+    kw = dict(S0=100.0, K=40.0, r=0.03, sigma=0.15, T=1.0)
+    price, se, v = gpu_price(amq, pricer, None, N=2048, M=30, basis=("monomial", 3), **kw)
+    ores, od = oracle_price(orc, None, N=2048, M=30, basis=("monomial", 3), **kw)
+    res = v["result"].cpu().numpy()
+    log(f"  skipped gpu {res[4]} oracle {ores.n_skipped}; price {price} vs {ores.price}")
+    assert res[4] == ores.n_skipped
+    assert abs(price - ores.price) <= TOL["fp64"]
+
+
+def test_deterministic_repeats(amq, pricer):
+    w = CONFIG1
+    ref = gpu_price(amq, pricer, w, dtype="fp64")[0]
+    for _ in range(10):
+        assert gpu_price(amq, pricer, w, dtype="fp64")[0] == ref
+    ref32 = gpu_price(amq, pricer, w, dtype="fp32")[0]
+    for _ in range(5):
+        assert gpu_price(amq, pricer, w, dtype="fp32")[0] == ref32
+
+
+def test_sync_entry_point_matches_async(amq, pricer):
+    w = CONFIG1
+    p = amq.make_params(**w.params())
+    b = amq.make_basis(*w.basis)
+    a = amq.am_price_american(p, w.n_paths, w.n_dates, b, "fp64")
+    c = pricer.price(p, w.n_paths, w.n_dates, b, "fp64")
+    assert a == c
+
+
+def test_bounded_wait_reports_timeout(amq, orc, pricer):
+    # force the device-side barrier waits to give up almost at once; every
+    # workgroup must still exit and the call must report AM_ETIMEOUT (or, if
+    # no wait ever had to poll twice, succeed) -- then work normally again
+    w = CONFIG1
+    p = amq.make_params(**w.params())
+    b = amq.make_basis(*w.basis)
+    amq.am_debug_set_spin_limit(1)
+    try:
+        try:
+            pricer.price(p, w.n_paths, w.n_dates, b, "fp64")
+            outcome = "ok"
+        except amq.AmError as e:
+            assert e.code == amq.AM_ETIMEOUT
+            outcome = "timeout"
+    finally:
+        amq.am_debug_set_spin_limit(0)
+    log(f"  tiny spin limit -> {outcome}")
+    ref = gpu_price(amq, pricer, w, dtype="fp64")[0]
+    ores, _ = oracle_price(orc, w)
+    assert abs(ref - ores.price) <= TOL["fp64"]
+
+
+def test_too_many_paths_rejected(amq):
+    mx = amq.am_max_paths("fp32")
+    assert mx >= 1 << 24
+    p = amq.make_params(100.0, 100.0, 0.05, 0.3, 1.0)
+    with pytest.raises(amq.AmError) as e:
+        amq.am_price_american(p, mx * 4, 4, amq.make_basis("monomial", 2), "fp32")
+    assert e.value.code in (amq.AM_EDIM, amq.AM_ENOMEM)

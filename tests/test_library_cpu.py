@@ -1,0 +1,124 @@
+"""CPU checks of the HIP library's host side: it loads, exports every symbol
+the header declares, lays out workspaces sanely, rejects bad arguments before
+touching a device, and builds a bridge schedule with Brownian covariance."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amqmc.h")
+
+
+@pytest.fixture(scope="module")
+def amq():
+    import paper_1205_0106_amd as amq
+    if not os.path.exists(amq.LIB_PATH):
+        pytest.skip("libamqmc.so not built")
+    amq.lib()
+    return amq
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(am_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(amq):
+    names = _declared_functions()
+    assert len(names) >= 10
+    L = ctypes.CDLL(amq.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), f"{n} not exported"
+
+
+def test_max_dates(amq):
+    assert amq.am_max_dates() >= 365
+
+
+@pytest.mark.parametrize("N,M,dt", [(16384, 50, "fp64"), (1 << 20, 100, "fp32"), (1000, 3, "fp64")])
+def test_workspace_layout(amq, N, M, dt):
+    b = amq.make_basis("monomial", 2)
+    lay = amq.am_workspace_layout(N, M, b, dt)
+    s = 8 if dt == "fp64" else 4
+    assert lay.ld >= N and lay.ld % 32768 == 0
+    assert lay.off_S == 0 and lay.off_PV >= M * lay.ld * s
+    for off in (lay.off_PV, lay.off_rec, lay.off_result):
+        assert off % 256 == 0
+    assert lay.total == amq.am_workspace_bytes(N, M, b, dt) and lay.total > lay.off_result
+
+
+@pytest.mark.parametrize("bad", [
+    dict(S0=-1.0), dict(K=0.0), dict(sigma=0.0), dict(T=float("nan")), dict(r=float("inf")),
+])
+def test_invalid_params_rejected_before_device(amq, bad):
+    kw = dict(S0=36.0, K=40.0, r=0.06, sigma=0.2, T=1.0)
+    kw.update(bad)
+    p = amq.make_params(**kw)
+    with pytest.raises(amq.AmError) as e:
+        amq.am_price_american(p, 4096, 10, amq.make_basis("monomial", 2), "fp64")
+    assert e.value.code == amq.AM_EINVAL
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(n_paths=2, n_dates=10, degree=2), -1),       # fewer paths than p + 1
+    (dict(n_paths=4096, n_dates=0, degree=2), -1),
+    (dict(n_paths=4096, n_dates=100000, degree=2), -4),
+    (dict(n_paths=4096, n_dates=641, degree=2), -4),
+    (dict(n_paths=4096, n_dates=10, degree=7), -1),
+    (dict(n_paths=1 << 33, n_dates=10, degree=2), -4),
+])
+def test_invalid_shapes_rejected(amq, args, code):
+    p = amq.make_params(36.0, 40.0, 0.06, 0.2, 1.0)
+    with pytest.raises(amq.AmError) as e:
+        amq.am_price_american(p, args["n_paths"], args["n_dates"],
+                              amq.make_basis("monomial", args["degree"]), "fp64")
+    assert e.value.code == code
+
+
+def test_bad_enums_rejected(amq):
+    p = amq.make_params(36.0, 40.0, 0.06, 0.2, 1.0)
+    with pytest.raises(amq.AmError):
+        amq.am_price_american(p, 4096, 10, amq.am_basis(5, 2), "fp64")
+    with pytest.raises(amq.AmError):
+        amq.am_price_american(p, 4096, 10, amq.make_basis("monomial", 2), 7)
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 7, 50, 100, 252, 365, 640])
+def test_schedule_gives_brownian_covariance(amq, M):
+    # apply the library's depth-first schedule to unit vectors: the map W = Bz
+    # must have covariance min(t_i, t_j) (dt = 1 units here)
+    sc = amq.am_debug_schedule(M)
+    B = np.zeros((M + 1, M))      # row = date 0..M, col = Sobol dim
+    for q in range(M):
+        m, l, r = sc["m"][q], sc["left"][q], sc["right"][q]
+        B[m] = sc["wl"][q] * B[l] + sc["wr"][q] * B[r]
+        B[m, sc["dim"][q]] += sc["sd"][q]
+    cov = B[1:] @ B[1:].T
+    t = np.arange(1, M + 1, dtype=float)
+    assert np.abs(cov - np.minimum.outer(t, t)).max() < 1e-9 * M
+
+
+@pytest.mark.parametrize("M", [1, 5, 50, 365])
+def test_schedule_dimension_numbering_is_breadth_first(amq, orc, M):
+    # each date must read the same Sobol dimension as in the breadth-first
+    # bisection (the construction order may differ)
+    sc = amq.am_debug_schedule(M)
+    om, ol, orr = orc.bridge_nodes(M)
+    want = {int(m): q for q, m in enumerate(om)}
+    for q in range(M):
+        assert want[int(sc["m"][q])] == sc["dim"][q]
+        if q > 0:
+            assert (sc["left"][q], sc["right"][q]) == (ol[sc["dim"][q]], orr[sc["dim"][q]])
+
+
+def test_binding_raises_when_library_missing(monkeypatch):
+    import paper_1205_0106_amd as amq
+    monkeypatch.setattr(amq, "_lib", None)
+    monkeypatch.setattr(amq, "LIB_PATH", "/nonexistent/libamqmc.so")
+    with pytest.raises(ImportError):
+        amq.lib()

@@ -36,10 +36,10 @@ MUTANTS = [
      "double sd = (tm - tl) * (tr - tm) / (tr - tl);"),
     ("bridge root scale", "W[M] = sqrt(T) * z[0];", "W[M] = T * z[0];"),
     ("bridge midpoint rounding", "int m = (l + r) / 2;\n        m_out[q] = m;", "int m = (l + r + 1) / 2;\n        m_out[q] = m;"),
-    ("drift sign", "double drift = p->r - 0.5 * p->sigma * p->sigma;\n    for (int64_t i = 0; i < N; ++i) {\n        uint64_t n = (uint64_t)i + 1u;                 /* skip the origin */",
-     "double drift = p->r + 0.5 * p->sigma * p->sigma;\n    for (int64_t i = 0; i < N; ++i) {\n        uint64_t n = (uint64_t)i + 1u;                 /* skip the origin */"),
-    ("origin not skipped", "uint64_t n = (uint64_t)i + 1u;                 /* skip the origin */",
-     "uint64_t n = (uint64_t)i;"),
+    ("drift sign", "double drift = p->r - 0.5 * p->sigma * p->sigma;\n    for (int64_t c = 0; c < count; ++c) {",
+     "double drift = p->r + 0.5 * p->sigma * p->sigma;\n    for (int64_t c = 0; c < count; ++c) {"),
+    ("origin not skipped", "uint64_t n = (uint64_t)(first + c) + 1u;       /* skip the origin */",
+     "uint64_t n = (uint64_t)(first + c);"),
     ("target not discounted", "double y = CF[i] * exp(-p->r * (t[tau[i]] - t[k]));", "double y = CF[i];"),
     ("target discounted to t0", "double y = CF[i] * exp(-p->r * (t[tau[i]] - t[k]));",
      "double y = CF[i] * exp(-p->r * t[tau[i]]);"),
