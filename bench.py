@@ -39,7 +39,29 @@ def parse():
     ap.add_argument("--dtype", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-side", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib, steps):
+    """Plain device copies of a known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the pricing kernels."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_calibration_bytes_read_per_copy": n * 4,
+                      "bytes_written_per_copy": n * 4, "copies": steps + 2,
+                      "GBps": 2 * n * 4 * steps / dt / 1e9}), flush=True)
 
 
 def time_steps(amq, pricer, p, b, w, dtype, steps, warmup):
@@ -101,6 +123,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, args.steps)
+        return
     import torch
     import paper_1205_0106_amd as amq
     from paper_1205_0106_amd.workloads import CONFIGS

@@ -8,7 +8,7 @@ namespace amq {
 
 constexpr int kWG = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
-constexpr int kMaxSlots = 20;     // bridge register window (tree depth + 2)
+constexpr int kMaxSlots = 16;     // bridge register window (tree depth + 2; depth <= 10 for 640 dates)
 constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS) bound this
 constexpr int kRec = 32;          // doubles per date record
 constexpr int kPartStride = 32;   // doubles per workgroup partial-sum slot
