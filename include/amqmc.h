@@ -112,6 +112,33 @@ int am_price_american_ex(const am_params *params, int64_t n_paths, int32_t n_dat
                          am_basis basis, int32_t dtype, void *d_workspace, size_t ws_bytes,
                          void *hip_stream, double *h_out);
 
+/* Randomised quasi-Monte Carlo (reading of Section III.D, where the
+ * quasi-random arrays are permuted by a linear congruential generator to make
+ * the per-path samples statistically independent): n_rep independent
+ * pricings, replicate r using the points x XOR h_shifts[r*n_dates + j] in
+ * dimension j (a random digital shift; the caller draws the shifts, e.g.
+ * uniform 32-bit words) mapped to cell midpoints u = (x + 1/2) 2^-32.
+ * h_out (n_rep + 2 doubles, or NULL for asynchronous use) receives the mean
+ * of the replicate prices, sd/sqrt(n_rep) across replicates (an honest
+ * error bar), then the replicate prices.  1 <= n_rep <= 64.  Workspace as in
+ * am_price_american_ex. */
+int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates,
+                           am_basis basis, int32_t dtype, int32_t n_rep, const uint32_t *h_shifts,
+                           void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out);
+
+/* The paper's own estimator (Section V, eqs. (10)-(11)) on the same
+ * quasi-random paths: n_points exercise points t_i = i T/(n_points+1); at the
+ * last point the value is max(h(S), Black–Scholes value over the remaining
+ * interval), earlier c_i = max(h(S_i), exp(-r dt) c_{i+1}); price =
+ * exp(-r dt) * mean(c_1) and its naive standard error.  Perfect foresight
+ * along each path, so an upper-bias estimate (the paper calls it an upper
+ * bound).  Uses the workspace of am_workspace_bytes(n_paths, n_points, any
+ * basis, dtype); params->allow_exercise is ignored.  Stream, workspace and
+ * h_out semantics as in am_price_american_ex. */
+int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n_points,
+                             int32_t dtype, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                             double *h_out);
+
 /* Thread-local description of the last failure on this thread; valid until
  * the next call on the same thread.  Never NULL. */
 const char *am_last_error(void);

@@ -122,6 +122,15 @@ def _configure(L):
                                   P(ctypes.c_double)]
     L.or_paths.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64, ctypes.c_int,
                            P(ctypes.c_double)]
+    L.or_inv_normal_mid_u32.argtypes = [ctypes.c_uint32]
+    L.or_inv_normal_mid_u32.restype = ctypes.c_double
+    L.or_price_american_shifted.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            P(ctypes.c_uint32), P(_Result), P(ctypes.c_double),
+                                            P(ctypes.c_int32), P(ctypes.c_double)]
+    L.or_paths_range_shifted.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint32),
+                                         P(ctypes.c_double)]
     L.or_paths_range.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int, P(ctypes.c_double)]
     L.or_basis_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -291,6 +300,33 @@ def price_american(S0, K, r, sigma, T, N: int, M: int, *, is_call=False, allow_e
     if detail:
         return out, dict(beta=beta, nitm=nitm, pv=pv)
     return out
+
+
+def inv_normal_mid_u32(x: int) -> float:
+    return lib().or_inv_normal_mid_u32(int(x))
+
+
+def price_american_rqmc(S0, K, r, sigma, T, N: int, M: int, shifts: np.ndarray, *, is_call=False,
+                        allow_exercise=True, kind=MONOMIAL, degree=2):
+    """Randomised QMC: one price per digital-shift replicate (shifts: uint32
+    [R][M]).  Returns (mean, sd/sqrt(R), per-replicate prices)."""
+    p = _params(S0, K, r, sigma, T, is_call, allow_exercise)
+    V = directions(M)
+    shifts = np.ascontiguousarray(shifts, dtype=np.uint32)
+    prices = []
+    for row in shifts:
+        res = _Result()
+        row = np.ascontiguousarray(row)
+        rc = lib().or_price_american_shifted(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, kind,
+                                             degree, _ptr(row, ctypes.c_uint32), ctypes.byref(res),
+                                             None, None, None)
+        if rc != 0:
+            raise RuntimeError("or_price_american_shifted failed")
+        prices.append(res.price)
+    prices = np.array(prices)
+    R = len(prices)
+    se = prices.std(ddof=1) / np.sqrt(R) if R > 1 else 0.0
+    return float(prices.mean()), float(se), prices
 
 
 def paper_estimator(S0, K, r, sigma, T, N: int, m: int, *, is_call=True) -> OracleResult:

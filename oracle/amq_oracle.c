@@ -149,6 +149,19 @@ double or_inv_normal_u32(uint32_t x)
     return bsm_tail((4294967296.0 - (double)x) * s);
 }
 
+/* Randomised points (reading of Section III.D's permuted quasi-random arrays:
+ * a random digital shift x' = x XOR s_j per dimension).  A shifted integer can
+ * be 0, so shifted points sit at cell midpoints u = (x' + 1/2) 2^-32, exact in
+ * binary64; the upper tail again uses the exact complement. */
+double or_inv_normal_mid_u32(uint32_t x)
+{
+    const double s = 1.0 / 4294967296.0;
+    double y = ((double)x + 0.5 - 2147483648.0) * s;
+    if (fabs(y) < 0.42) return bsm_central(y);
+    if (y < 0.0) return -bsm_tail(((double)x + 0.5) * s);
+    return bsm_tail((4294967296.0 - (double)x - 0.5) * s);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Brownian bridge (the construction of reference [13]).                     */
 /* Node 0 sets W(t_M); then intervals are bisected breadth first, left       */
@@ -199,9 +212,19 @@ void or_bridge_apply(int M, double T, const double *z, double *W)
 /* ------------------------------------------------------------------------ */
 /* GBM paths on the exercise grid (Section V, eq. (9), exact lognormal map). */
 /* ------------------------------------------------------------------------ */
-/* Paths first..first+count-1 into S[M][count]. */
+/* Paths first..first+count-1 into S[M][count]; shift (nullable, [M]) applies a
+ * digital shift to dimension q and maps points to cell midpoints. */
+int or_paths_range_shifted(const or_params *p, const uint32_t *V, int64_t first, int64_t count,
+                           int M, const uint32_t *shift, double *S);
+
 int or_paths_range(const or_params *p, const uint32_t *V, int64_t first, int64_t count, int M,
                    double *S)
+{
+    return or_paths_range_shifted(p, V, first, count, M, NULL, S);
+}
+
+int or_paths_range_shifted(const or_params *p, const uint32_t *V, int64_t first, int64_t count,
+                           int M, const uint32_t *shift, double *S)
 {
     double *z = (double *)malloc(sizeof(double) * (size_t)M);
     double *W = (double *)malloc(sizeof(double) * (size_t)(M + 1));
@@ -209,7 +232,9 @@ int or_paths_range(const or_params *p, const uint32_t *V, int64_t first, int64_t
     double drift = p->r - 0.5 * p->sigma * p->sigma;
     for (int64_t c = 0; c < count; ++c) {
         uint64_t n = (uint64_t)(first + c) + 1u;       /* skip the origin */
-        for (int q = 0; q < M; ++q) z[q] = or_inv_normal_u32(or_sobol_int(V, q, n));
+        for (int q = 0; q < M; ++q)
+            z[q] = shift ? or_inv_normal_mid_u32(or_sobol_int(V, q, n) ^ shift[q])
+                         : or_inv_normal_u32(or_sobol_int(V, q, n));
         or_bridge_apply(M, p->T, z, W);
         for (int k = 1; k <= M; ++k) {
             double tk = (double)k * p->T / (double)M;
@@ -391,10 +416,18 @@ int or_price_american(const or_params *p, const uint32_t *V, int64_t N, int M,
                       int kind, int degree, or_result *res,
                       double *beta_out, int32_t *nitm_out, double *pv_out)
 {
+    return or_price_american_shifted(p, V, N, M, kind, degree, NULL, res, beta_out, nitm_out,
+                                     pv_out);
+}
+
+int or_price_american_shifted(const or_params *p, const uint32_t *V, int64_t N, int M,
+                              int kind, int degree, const uint32_t *shift, or_result *res,
+                              double *beta_out, int32_t *nitm_out, double *pv_out)
+{
     if (N < 1 || M < 1) return -1;
     double *S = (double *)malloc(sizeof(double) * (size_t)N * (size_t)M);
     if (!S) return -2;
-    int rc = or_paths(p, V, N, M, S);
+    int rc = or_paths_range_shifted(p, V, 0, N, M, shift, S);
     if (rc == 0) rc = or_lsm_on_paths(S, N, M, p, kind, degree, res, beta_out,
                                       nitm_out, NULL, pv_out);
     free(S);

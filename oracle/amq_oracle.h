@@ -57,6 +57,7 @@ void or_sobol_block(const uint32_t *V, int ndim, uint64_t first, int64_t count,
 /* Moro (Beasley–Springer–Moro) inverse cumulative normal. */
 double or_inv_normal(double u);
 double or_inv_normal_u32(uint32_t x);
+double or_inv_normal_mid_u32(uint32_t x);
 
 /* Brownian bridge, breadth-first bisection. */
 int or_bridge_nodes(int M, int32_t *m, int32_t *left, int32_t *right);
@@ -66,6 +67,8 @@ void or_bridge_apply(int M, double T, const double *z, double *W);
 int or_paths(const or_params *p, const uint32_t *V, int64_t N, int M, double *S);
 int or_paths_range(const or_params *p, const uint32_t *V, int64_t first, int64_t count, int M,
                    double *S);
+int or_paths_range_shifted(const or_params *p, const uint32_t *V, int64_t first, int64_t count,
+                           int M, const uint32_t *shift, double *S);
 
 /* Basis functions of x = S/K. Returns the number of functions. */
 int or_basis_eval(int kind, int degree, double x, double *psi);
@@ -80,6 +83,11 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
 int or_price_american(const or_params *p, const uint32_t *V, int64_t N, int M,
                       int kind, int degree, or_result *res,
                       double *beta_out, int32_t *nitm_out, double *pv_out);
+
+/* Same, on digitally shifted points (shift: [M], one word per dimension). */
+int or_price_american_shifted(const or_params *p, const uint32_t *V, int64_t N, int M,
+                              int kind, int degree, const uint32_t *shift, or_result *res,
+                              double *beta_out, int32_t *nitm_out, double *pv_out);
 
 /* The paper's own estimator: Black–Scholes over the last interval, then a
  * per-path backward maximum (eqs. (10)-(11)). */

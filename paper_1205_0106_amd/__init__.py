@@ -85,6 +85,13 @@ def lib():
         L.am_price_american_ex.argtypes = [P(am_params), i64, i32, am_basis, i32, ctypes.c_void_p,
                                            sz, ctypes.c_void_p, P(dbl)]
         L.am_price_american_ex.restype = ctypes.c_int
+        L.am_price_american_rqmc.argtypes = [P(am_params), i64, i32, am_basis, i32, i32,
+                                             P(ctypes.c_uint32), ctypes.c_void_p, sz,
+                                             ctypes.c_void_p, P(dbl)]
+        L.am_price_american_rqmc.restype = ctypes.c_int
+        L.am_price_paper_estimator.argtypes = [P(am_params), i64, i32, i32, ctypes.c_void_p, sz,
+                                               ctypes.c_void_p, P(dbl)]
+        L.am_price_paper_estimator.restype = ctypes.c_int
         L.am_last_error.argtypes = []
         L.am_last_error.restype = ctypes.c_char_p
         L.am_max_dates.argtypes = []
@@ -159,6 +166,39 @@ def am_price_american_ex(params: am_params, n_paths: int, n_dates: int, basis: a
     _check(lib().am_price_american_ex(ctypes.byref(params), int(n_paths), int(n_dates), basis,
                                       _dtype(dtype), ctypes.c_void_p(workspace.data_ptr()),
                                       workspace.numel(), ctypes.c_void_p(stream.cuda_stream), out))
+    if wait:
+        return out[0], out[1]
+    return None
+
+
+def am_price_american_rqmc(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
+                           shifts, workspace, stream=None):
+    """Randomised QMC (digital shifts, uint32 [R][n_dates]); returns
+    (mean, error bar, replicate prices)."""
+    import numpy as np
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    sh = np.ascontiguousarray(shifts, dtype=np.uint32)
+    R = sh.shape[0]
+    out = (ctypes.c_double * (R + 2))()
+    _check(lib().am_price_american_rqmc(ctypes.byref(params), int(n_paths), int(n_dates), basis,
+                                        _dtype(dtype), R, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                        ctypes.c_void_p(stream.cuda_stream), out))
+    return out[0], out[1], np.array(out[2:R + 2])
+
+
+def am_price_paper_estimator(params: am_params, n_paths: int, n_points: int, dtype, workspace,
+                             stream=None, wait: bool = True):
+    """The paper's eqs. (10)-(11) estimator on the GPU (torch workspace/stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    out = (ctypes.c_double * 2)() if wait else None
+    _check(lib().am_price_paper_estimator(ctypes.byref(params), int(n_paths), int(n_points),
+                                          _dtype(dtype), ctypes.c_void_p(workspace.data_ptr()),
+                                          workspace.numel(), ctypes.c_void_p(stream.cuda_stream), out))
     if wait:
         return out[0], out[1]
     return None
@@ -243,6 +283,16 @@ class Pricer:
         nbytes = am_workspace_bytes(n_paths, n_dates, basis, dtype)
         ws = self.workspace(nbytes)
         return am_price_american_ex(params, n_paths, n_dates, basis, dtype, ws, self.stream, wait)
+
+    def price_rqmc(self, params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype, shifts):
+        nbytes = am_workspace_bytes(n_paths, n_dates, basis, dtype)
+        ws = self.workspace(nbytes)
+        return am_price_american_rqmc(params, n_paths, n_dates, basis, dtype, shifts, ws, self.stream)
+
+    def price_paper(self, params: am_params, n_paths: int, n_points: int, dtype, wait: bool = True):
+        nbytes = am_workspace_bytes(n_paths, n_points, make_basis("monomial", 0), dtype)
+        ws = self.workspace(nbytes)
+        return am_price_paper_estimator(params, n_paths, n_points, dtype, ws, self.stream, wait)
 
     def views(self, n_paths: int, n_dates: int, basis: am_basis, dtype):
         """Torch views of the last call's paths, PV, per-date records, result."""

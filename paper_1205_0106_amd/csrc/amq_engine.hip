@@ -51,7 +51,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     int64_t ld;
     size_t s_bytes;  // element size
-    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, total;
+    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, off_shift, off_rep, total;
 };
 
 Layout make_layout(int64_t N, int32_t M, int32_t dtype)
@@ -66,6 +66,8 @@ Layout make_layout(int64_t N, int32_t M, int32_t dtype)
     L.off_rec = o;    o = align256(o + (size_t)(M + 1) * amq::kRec * 8);
     L.off_datec = o;  o = align256(o + (size_t)(M + 1) * sizeof(amq::DateConst));
     L.off_result = o; o = align256(o + 8 * 8 + 16 * 4);   // result[8] then sync[16]
+    L.off_shift = o;  o = align256(o + (size_t)amq::kMaxReps * M * 4);
+    L.off_rep = o;    o = align256(o + (size_t)amq::kMaxReps * 8);
     L.total = o;
     return L;
 }
@@ -268,7 +270,7 @@ int prof_slot(ProfRec **out)
 
 // Enqueue both kernels; result stays in the workspace.
 int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, int32_t dtype,
-            char *ws, const Layout &L, hipStream_t stream)
+            char *ws, const Layout &L, hipStream_t stream, int rep = -1, int n_rep = 0)
 {
     const int fp64 = dtype == AM_FP64;
     Plan plan;
@@ -296,6 +298,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     const double dt = p->T / (double)M;
     ga.mu = (p->r - 0.5 * p->sigma * p->sigma) * dt;
     ga.vol = p->sigma * sqrt(dt);
+    ga.shift = rep >= 0 ? (const uint32_t *)(ws + L.off_shift) + (size_t)rep * M : nullptr;
     ProfRec *pr = nullptr;
     if (g_prof.on) {
         int prc = prof_slot(&pr);
@@ -320,6 +323,9 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     sa.laguerre = b.kind == AM_BASIS_LAGUERRE; sa.degree = b.degree;
     sa.S0 = p->S0; sa.K = p->K;
     sa.spin_limit = g_spin_limit ? g_spin_limit : kDefaultSpin;
+    sa.rep_out = rep >= 0 ? (double *)(ws + L.off_rep) : nullptr;
+    sa.rep = rep;
+    sa.n_rep = n_rep;
     hipError_t e = amq::launch_sweep(sa, fp64, plan.ppt, stream);
     if (e != hipSuccess)
         return fail(AM_EDEVICE, "sweep launch (ppt %d, groups %d) failed: %s", plan.ppt, plan.G,
@@ -444,6 +450,86 @@ int am_price_american(const am_params *params, int64_t n_paths, int32_t n_dates,
     *price = out[0];
     *std_err = out[1];
     return AM_OK;
+}
+
+int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                           int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
+                           size_t ws_bytes, void *hip_stream, double *h_out)
+{
+    int rc = validate(params, n_paths, n_dates, basis, dtype);
+    if (rc) return rc;
+    if (n_rep < 1 || n_rep > amq::kMaxReps || !h_shifts)
+        return fail(AM_EINVAL, "n_rep must be in [1, %d] and shifts non-NULL", amq::kMaxReps);
+    Layout L = make_layout(n_paths, n_dates, dtype);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", L.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    char *ws = (char *)d_workspace;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemcpyAsync(ws + L.off_shift, h_shifts, (size_t)n_rep * n_dates * 4,
+                           hipMemcpyHostToDevice, stream));
+    for (int r = 0; r < n_rep; ++r) {
+        rc = enqueue(st, params, n_paths, n_dates, basis, dtype, ws, L, stream, r, n_rep);
+        if (rc) return rc;
+    }
+    if (!h_out) return AM_OK;
+    rc = fetch_result(ws, L, stream, h_out);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(h_out + 2, ws + L.off_rep, (size_t)n_rep * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return AM_OK;
+}
+
+int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n_points,
+                             int32_t dtype, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                             double *h_out)
+{
+    am_basis b0 = {AM_BASIS_MONOMIAL, 0};
+    int rc = validate(params, n_paths, n_points, b0, dtype);
+    if (rc) return rc;
+    Layout L = make_layout(n_paths, n_points, dtype);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", L.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    const amq::BridgeNode *sched = nullptr;
+    rc = get_schedule(st, n_points, &sched);
+    if (rc) return rc;
+    char *ws = (char *)d_workspace;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const int fp64 = dtype == AM_FP64;
+    const double dt = params->T / (double)(n_points + 1);
+    amq::GenArgs ga;
+    memset(&ga, 0, sizeof ga);
+    ga.S = ws + L.off_S;
+    ga.V = st->d_V;
+    ga.sched = sched;
+    ga.datec = (amq::DateConst *)(ws + L.off_datec);
+    ga.sync = (uint32_t *)(ws + L.off_result + 64);
+    ga.N = n_paths; ga.ld = L.ld; ga.nblocks = L.ld / 64; ga.M = n_points;
+    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
+    ga.R = (int32_t)(R < 1 ? 1 : R);
+    ga.what = 0;
+    ga.S0 = params->S0; ga.K = params->K; ga.r = params->r; ga.sigma = params->sigma;
+    ga.T = dt * (double)n_points;                       // horizon t_m = m dt
+    ga.mu = (params->r - 0.5 * params->sigma * params->sigma) * dt;
+    ga.vol = params->sigma * sqrt(dt);
+    HIP_TRY(amq::launch_generate(ga, fp64, stream));
+    amq::PaperArgs pa;
+    memset(&pa, 0, sizeof pa);
+    pa.S = ws + L.off_S;
+    pa.part = (double *)(ws + L.off_part);
+    pa.ticket = (uint32_t *)(ws + L.off_result + 64) + 4;
+    pa.result = (double *)(ws + L.off_result);
+    pa.N = n_paths; pa.ld = L.ld; pa.m = n_points; pa.is_call = params->is_call;
+    pa.K = params->K; pa.r = params->r; pa.sigma = params->sigma; pa.dt = dt;
+    HIP_TRY(amq::launch_paper(pa, fp64, stream));
+    if (!h_out) return AM_OK;
+    return fetch_result(ws, L, stream, h_out);
 }
 
 int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left, int32_t *right,

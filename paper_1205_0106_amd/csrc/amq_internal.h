@@ -13,6 +13,7 @@ constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS
 constexpr int kRec = 32;          // doubles per date record
 constexpr int kPartStride = 32;   // doubles per workgroup partial-sum slot
 constexpr int kMaxGroups = 2048;  // partial-sum slots in the workspace
+constexpr int kMaxReps = 64;      // randomised QMC replicates per call
 constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
 
 // One node of the Brownian bridge, in depth-first construction order.  The
@@ -49,6 +50,7 @@ struct GenArgs {
     int32_t M, R;             // dates, 64-path blocks per wave
     int32_t what;             // 0 paths, 1 sobol ints, 2 normals (debug)
     int32_t pad;
+    const uint32_t *shift;    // [M] digital shift (randomised QMC) or nullptr
     double S0, K, r, sigma, T;
     double mu, vol;           // (r - sigma^2/2) dt, sigma sqrt(dt)
 };
@@ -67,6 +69,18 @@ struct SweepArgs {
     double S0, K;
     uint32_t spin_limit;
     int32_t pad;
+    double *rep_out;          // randomised QMC: replicate prices [n_rep] or nullptr
+    int32_t rep, n_rep;
+};
+
+struct PaperArgs {
+    const void *S;            // [m][ld] T, dates t_i = i dt
+    double *part;             // [kMaxGroups][kPartStride]
+    uint32_t *ticket;         // zeroed by the generation kernel
+    double *result;           // [8]
+    int64_t N, ld;
+    int32_t m, is_call;
+    double K, r, sigma, dt;
 };
 
 // Launchers (defined with the kernels).
@@ -76,5 +90,6 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s);
 // Workgroups of the sweep kernel that fit on one CU for (fp64, ppt, degree).
 int sweep_blocks_per_cu(int fp64, int ppt, int degree);
 size_t generate_lds_bytes(int M);
+hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
 
 }  // namespace amq

@@ -94,9 +94,65 @@ __device__ __forceinline__ double inv_normal_f64(uint32_t x)
     return y < 0.0 ? -v : v;
 }
 
-template <typename T> __device__ __forceinline__ T inv_normal(uint32_t x);
-template <> __device__ __forceinline__ float inv_normal<float>(uint32_t x) { return inv_normal_f32(x); }
-template <> __device__ __forceinline__ double inv_normal<double>(uint32_t x) { return inv_normal_f64(x); }
+// Shifted (randomised) points sit at cell midpoints u = (x + 1/2) 2^-32, so a
+// shifted integer 0 still maps to a finite normal.
+__device__ __forceinline__ float inv_normal_mid_f32(uint32_t x)
+{
+    const float s = 0x1p-32f;
+    const int32_t d = (int32_t)(x - 0x80000000u);
+    const float y = ((float)d + 0.5f) * s;
+    const float r = y * y;
+    const float num = y * fmaf(fmaf(fmaf((float)AMQ_A3, r, (float)AMQ_A2), r, (float)AMQ_A1), r,
+                               (float)AMQ_A0);
+    const float den = fmaf(fmaf(fmaf(fmaf((float)AMQ_B3, r, (float)AMQ_B2), r, (float)AMQ_B1), r,
+                                (float)AMQ_B0), r, 1.0f);
+    const float zc = num * __builtin_amdgcn_rcpf(den);
+    const uint32_t tq = d < 0 ? x : 0u - x;
+    const float q = fmaf((float)tq, s, d < 0 ? 0x1p-33f : -0x1p-33f);
+    const float ln2 = 0.69314718055994531f;
+    const float t = __builtin_amdgcn_logf(-__builtin_amdgcn_logf(q) * ln2) * ln2;
+    float v = (float)AMQ_C8;
+    v = fmaf(v, t, (float)AMQ_C7);
+    v = fmaf(v, t, (float)AMQ_C6);
+    v = fmaf(v, t, (float)AMQ_C5);
+    v = fmaf(v, t, (float)AMQ_C4);
+    v = fmaf(v, t, (float)AMQ_C3);
+    v = fmaf(v, t, (float)AMQ_C2);
+    v = fmaf(v, t, (float)AMQ_C1);
+    v = fmaf(v, t, (float)AMQ_C0);
+    const float zt = d < 0 ? -v : v;
+    return fabsf(y) < 0.42f ? zc : zt;
+}
+
+__device__ __forceinline__ double inv_normal_mid_f64(uint32_t x)
+{
+    const double s = 0x1p-32;
+    const double y = ((double)x + 0.5 - 2147483648.0) * s;
+    if (fabs(y) < 0.42) {
+        const double r = y * y;
+        const double num = y * (((AMQ_A3 * r + AMQ_A2) * r + AMQ_A1) * r + AMQ_A0);
+        const double den = (((AMQ_B3 * r + AMQ_B2) * r + AMQ_B1) * r + AMQ_B0) * r + 1.0;
+        return num / den;
+    }
+    const double q = y < 0.0 ? ((double)x + 0.5) * s : (4294967296.0 - (double)x - 0.5) * s;
+    const double t = log(-log(q));
+    double v = AMQ_C8;
+    v = v * t + AMQ_C7;
+    v = v * t + AMQ_C6;
+    v = v * t + AMQ_C5;
+    v = v * t + AMQ_C4;
+    v = v * t + AMQ_C3;
+    v = v * t + AMQ_C2;
+    v = v * t + AMQ_C1;
+    v = v * t + AMQ_C0;
+    return y < 0.0 ? -v : v;
+}
+
+template <typename T, bool MID> __device__ __forceinline__ T inv_normal(uint32_t x);
+template <> __device__ __forceinline__ float inv_normal<float, false>(uint32_t x) { return inv_normal_f32(x); }
+template <> __device__ __forceinline__ double inv_normal<double, false>(uint32_t x) { return inv_normal_f64(x); }
+template <> __device__ __forceinline__ float inv_normal<float, true>(uint32_t x) { return inv_normal_mid_f32(x); }
+template <> __device__ __forceinline__ double inv_normal<double, true>(uint32_t x) { return inv_normal_mid_f64(x); }
 
 size_t generate_lds_bytes(int M)
 {
@@ -118,9 +174,10 @@ size_t generate_lds_bytes(int M)
 // log2(M) + 2 live values; dimension order follows the breadth-first node
 // numbering, which only changes the order the Sobol dimensions are read.
 // ---------------------------------------------------------------------------
-template <typename T, int WHAT>
+template <typename T, int WHAT, bool MID>
 __global__ void __launch_bounds__(kWG)
-gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched)
+gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
+           const uint32_t *__restrict__ shift)
 {
     extern __shared__ uint32_t lds[];
     const int M = a.M;
@@ -197,12 +254,13 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
         for (int s = 0; s < M; ++s) {
             const BridgeNode nd = sched[s];
             const int j = nd.dim;
-            const uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
+            uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
+            if (MID) x ^= shift[j];
             if (WHAT == 1) {
                 if (valid) ((uint32_t *)a.S)[(size_t)j * a.ld + i] = x;
                 continue;
             }
-            const T z = inv_normal<T>(x);
+            const T z = inv_normal<T, MID>(x);
             if (WHAT == 2) {
                 if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = (double)z;
                 continue;
@@ -242,14 +300,21 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
     const int64_t waves = (a.nblocks + a.R - 1) / a.R;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const size_t lds = generate_lds_bytes(a.M);
+    const dim3 g((unsigned)grid), b(kWG);
+    const bool mid = a.shift != nullptr;
     if (a.what == 0) {
-        if (fp64) hipLaunchKernelGGL((gen_kernel<double, 0>), dim3((unsigned)grid), dim3(kWG), lds, s, a, a.V, a.sched);
-        else      hipLaunchKernelGGL((gen_kernel<float, 0>), dim3((unsigned)grid), dim3(kWG), lds, s, a, a.V, a.sched);
+        if (fp64) {
+            if (mid) hipLaunchKernelGGL((gen_kernel<double, 0, true>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else     hipLaunchKernelGGL((gen_kernel<double, 0, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        } else {
+            if (mid) hipLaunchKernelGGL((gen_kernel<float, 0, true>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else     hipLaunchKernelGGL((gen_kernel<float, 0, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        }
     } else if (a.what == 1) {
-        hipLaunchKernelGGL((gen_kernel<float, 1>), dim3((unsigned)grid), dim3(kWG), lds, s, a, a.V, a.sched);
+        hipLaunchKernelGGL((gen_kernel<float, 1, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
     } else {
-        if (fp64) hipLaunchKernelGGL((gen_kernel<double, 2>), dim3((unsigned)grid), dim3(kWG), lds, s, a, a.V, a.sched);
-        else      hipLaunchKernelGGL((gen_kernel<float, 2>), dim3((unsigned)grid), dim3(kWG), lds, s, a, a.V, a.sched);
+        if (fp64) hipLaunchKernelGGL((gen_kernel<double, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        else      hipLaunchKernelGGL((gen_kernel<float, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
     }
     return hipGetLastError();
 }
@@ -743,6 +808,20 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
             a.result[3] = t0;
             a.result[4] = skipped;
             a.result[5] = 0.0;
+            if (a.rep_out) {
+                // randomised QMC: replicate prices of earlier launches are
+                // visible (stream order); the last replicate aggregates
+                a.rep_out[a.rep] = price;
+                if (a.rep + 1 == a.n_rep) {
+                    double s1 = 0.0;
+                    for (int q = 0; q < a.n_rep; ++q) s1 += a.rep_out[q];
+                    const double m = s1 / (double)a.n_rep;
+                    double s2 = 0.0;
+                    for (int q = 0; q < a.n_rep; ++q) s2 += (a.rep_out[q] - m) * (a.rep_out[q] - m);
+                    a.result[0] = m;
+                    a.result[1] = a.n_rep > 1 ? sqrt(s2 / (double)(a.n_rep - 1) / (double)a.n_rep) : 0.0;
+                }
+            }
         }
     }
 }
@@ -802,6 +881,87 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
     const void *Sp = a.S;
     void *params[] = {(void *)&args, (void *)&Sp};
     return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3(kWG), params, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own estimator (Section V, eqs. (10)-(11)): on the grid
+// t_i = i dt, dt = T/(m+1), i = 1..m, the value at t_m is the larger of the
+// exercise value and the Black–Scholes value over the last interval dt
+// (eqs. (1)-(5)); going back, c_i = max(h(S_i), exp(-r dt) c_{i+1}); the price
+// is exp(-r dt) times the path mean of c_1 (eq. (6)).  Every path is
+// independent: one thread per path, no device-wide wait.  The paths come from
+// the generation kernel run with m dates and horizon m dt.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T cnd(T x);
+template <> __device__ __forceinline__ float cnd<float>(float x) { return 0.5f * erfcf(-x * 0.70710678118654752f); }
+template <> __device__ __forceinline__ double cnd<double>(double x) { return 0.5 * erfc(-x * 0.70710678118654752); }
+
+template <typename T>
+__device__ __forceinline__ T bs_value(T S, T K, T r, T sig, T tau, bool call)
+{
+    const T sq = sig * sqrt(tau);
+    const T d1 = (log(S / K) + (r + T(0.5) * sig * sig) * tau) / sq;
+    const T d2 = d1 - sq;
+    const T dk = K * exp(-r * tau);
+    return call ? S * cnd<T>(d1) - dk * cnd<T>(d2) : dk * cnd<T>(-d2) - S * cnd<T>(-d1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) paper_kernel(PaperArgs a, const T *__restrict__ S)
+{
+    __shared__ double s_red[kWaves][32];
+    __shared__ double s_red8[8][32];
+    __shared__ double s_tot[32];
+    __shared__ int s_flag[2];
+    const T K = (T)a.K, r = (T)a.r, sig = (T)a.sigma, dt = (T)a.dt;
+    const T disc = (T)exp(-a.r * a.dt);
+    const bool call = a.is_call != 0;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < a.N; i += (int64_t)gridDim.x * kWG) {
+        T v = T(0);
+        for (int k = a.m; k >= 1; --k) {
+            const T s = S[(size_t)(k - 1) * a.ld + i];
+            T h = call ? s - K : K - s;
+            h = h > T(0) ? h : T(0);
+            const T cont = (k == a.m) ? bs_value<T>(s, K, r, sig, dt, call) : disc * v;
+            v = h > cont ? h : cont;
+        }
+        const double c = (double)disc * (double)v;
+        acc[0] += c;
+        acc[1] += c * c;
+    }
+    group_sum<2>(acc, s_red);
+    if (threadIdx.x == 0) {
+        double *dst = a.part + (size_t)blockIdx.x * kPartStride;
+        dst[0] = acc[0];
+        dst[1] = acc[1];
+        const uint32_t old = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag[0] = (old + 1u == gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag[0]) return;
+    reduce_partials<2>(a.part, gridDim.x, s_tot, s_red8);
+    if (threadIdx.x == 0) {
+        const double n = (double)a.N;
+        const double mean = s_tot[0] / n;
+        double var = a.N > 1 ? (s_tot[1] - s_tot[0] * mean) / (n - 1.0) : 0.0;
+        if (var < 0.0) var = 0.0;
+        a.result[0] = mean;
+        a.result[1] = sqrt(var / n);
+        a.result[2] = mean;
+        a.result[3] = 0.0;
+        a.result[4] = 0.0;
+        a.result[5] = 0.0;
+    }
+}
+
+hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s)
+{
+    int64_t g = (a.N + kWG - 1) / kWG;
+    if (g > kMaxGroups) g = kMaxGroups;
+    if (fp64) hipLaunchKernelGGL((paper_kernel<double>), dim3((unsigned)g), dim3(kWG), 0, s, a, (const double *)a.S);
+    else      hipLaunchKernelGGL((paper_kernel<float>), dim3((unsigned)g), dim3(kWG), 0, s, a, (const float *)a.S);
+    return hipGetLastError();
 }
 
 }  // namespace amq

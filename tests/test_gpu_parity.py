@@ -302,3 +302,41 @@ def test_too_many_paths_rejected(amq):
     with pytest.raises(amq.AmError) as e:
         amq.am_price_american(p, mx * 4, 4, amq.make_basis("monomial", 2), "fp32")
     assert e.value.code in (amq.AM_EDIM, amq.AM_ENOMEM)
+
+
+# --------------------------------------------------------------------------
+# The paper's own estimator (Section V, eqs. (10)-(11))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,N,call", [(10, 1 << 16, True), (10, 1 << 16, False), (1, 1000, True),
+                                      (50, 4097, False), (3, 10, True)])
+def test_paper_estimator_matches_oracle(amq, orc, pricer, dtype, m, N, call):
+    kw = CONFIG1.params()
+    p = amq.make_params(**kw, is_call=call)
+    log(f"  paper estimator m={m} N={N} call={call} {dtype}")
+    price, se = pricer.price_paper(p, N, m, dtype)
+    want = orc.paper_estimator(**kw, N=N, m=m, is_call=call)
+    log(f"    gpu {price:.10f} oracle {want.price:.10f}")
+    assert abs(price - want.price) <= TOL[dtype]
+    assert price >= orc.bs_price(**kw, is_call=call) - TOL[dtype]
+
+
+# --------------------------------------------------------------------------
+# Randomised QMC (digital shifts): replicate prices and the error bar
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_rqmc_matches_oracle(amq, orc, pricer, dtype):
+    w = CONFIG1
+    R, N, M = 8, 1 << 12, 50
+    rng = np.random.default_rng(0x12050108)
+    sh = rng.integers(0, 2 ** 32, size=(R, M), dtype=np.uint64).astype(np.uint32)
+    p = amq.make_params(**w.params())
+    b = amq.make_basis(*w.basis)
+    log(f"  rqmc R={R} N={N} M={M} {dtype}")
+    mean, se, reps = pricer.price_rqmc(p, N, M, b, dtype, sh)
+    omean, ose, oreps = orc.price_american_rqmc(**w.params(), N=N, M=M, shifts=sh,
+                                                kind=orc.MONOMIAL, degree=2)
+    log(f"    gpu {mean:.8f} +- {se:.2e}  oracle {omean:.8f} +- {ose:.2e}")
+    assert np.abs(reps - oreps).max() <= TOL[dtype]
+    assert abs(mean - omean) <= TOL[dtype]
+    assert abs(se - ose) <= 0.05 * ose + TOL[dtype] / 10

@@ -59,6 +59,10 @@ MUTANTS = [
      "double var = N > 1 ? ks_val(&ss) / (double)(N) : 0.0;\n    double se = sqrt(var) / sqrt((double)N);"),
     ("bs d2 sign", "double d2 = d1 - sq;", "double d2 = d1 + sq;"),
     ("crr probability", "double q = (exp(r * dt) - d) / (u - d);", "double q = (exp(r * dt) - d) / (u + d);"),
+    ("digital shift ignored", "z[q] = shift ? or_inv_normal_mid_u32(or_sobol_int(V, q, n) ^ shift[q])",
+     "z[q] = shift ? or_inv_normal_mid_u32(or_sobol_int(V, q, n))"),
+    ("midpoint offset dropped", "double y = ((double)x + 0.5 - 2147483648.0) * s;",
+     "double y = ((double)x - 2147483648.0) * s;"),
     ("crr bermudan stride", "int ex = (style == OR_AMERICAN) || (style == OR_BERMUDAN && i % stride == 0);",
      "int ex = (style == OR_AMERICAN) || (style == OR_BERMUDAN && i % stride == 1);"),
 ]
@@ -93,6 +97,8 @@ def _pin_suite(orc):
         lambda: P.test_exercise_off_matches_black_scholes(orc, c4, 1 << 12),
         lambda: P.test_laguerre_basis_matches_scipy(orc),
         lambda: P.test_config1_lsm_close_to_bermudan_tree(orc),
+        lambda: P.test_midpoint_inverse_normal(orc),
+        lambda: P.test_rqmc_exercise_off_covers_black_scholes(orc),
     ]
 
 

@@ -230,3 +230,36 @@ def test_paper_estimator_is_an_upper_bound(orc):
     up = orc.paper_estimator(**CONFIG1, N=4096, m=10, is_call=False)
     lsm = orc.price_american(**CONFIG1, N=4096, M=11, kind=orc.MONOMIAL, degree=2)
     assert up.price > lsm.price
+
+
+# --------------------------------------------------------------------------
+# Randomised QMC (digital shifts, midpoint mapping)
+# --------------------------------------------------------------------------
+def _shifts(R, M, seed=0x12050108):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2 ** 32, size=(R, M), dtype=np.uint64).astype(np.uint32)
+
+
+def test_midpoint_inverse_normal(orc):
+    from scipy.special import ndtri
+    rng = np.random.default_rng(9)
+    xs = [0, 1, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 1] + [int(v) for v in rng.integers(0, 2 ** 32, 3000, dtype=np.uint64)]
+    for x in xs:
+        z = orc.inv_normal_mid_u32(x)
+        assert abs(z - ndtri((x + 0.5) / 2.0 ** 32)) < 3.2e-9
+        # exact odd symmetry: cell x and cell 2^32-1-x mirror about 1/2
+        assert orc.inv_normal_mid_u32((1 << 32) - 1 - x) == -z
+
+
+def test_rqmc_exercise_off_covers_black_scholes(orc):
+    mean, se, prices = orc.price_american_rqmc(**CONFIG1, N=1 << 12, M=16, shifts=_shifts(16, 16),
+                                               allow_exercise=False)
+    bs = orc.bs_price(**CONFIG1)
+    assert se > 0 and len(set(prices.tolist())) == 16
+    assert abs(mean - bs) < 4 * se
+
+
+def test_rqmc_lsm_close_to_bermudan_tree(orc):
+    mean, se, _ = orc.price_american_rqmc(**CONFIG1, N=1 << 12, M=50, shifts=_shifts(8, 50))
+    berm = orc.crr_price(**CONFIG1, n=5000, style=orc.BERMUDAN, M=50)
+    assert abs(mean - berm) < 0.03 + 3 * se
