@@ -139,6 +139,35 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
                              int32_t dtype, void *d_workspace, size_t ws_bytes, void *hip_stream,
                              double *h_out);
 
+/* ---------------------------------------------------------------------- */
+/* Batches: many options in one generation launch and one persistent sweep. */
+/* ---------------------------------------------------------------------- */
+
+/* One option of a batch. */
+typedef struct am_option {
+    am_params params;
+    int64_t n_paths;
+    int32_t n_dates;
+    int32_t reserved;       /* 0 */
+} am_option;
+
+/* Workspace bytes for am_price_batch on these options (0 if invalid). */
+size_t am_batch_workspace_bytes(const am_option *opts, int32_t n_opts, am_basis basis,
+                                int32_t dtype);
+
+/* Price n_opts options, each exactly as am_price_american_ex defines it
+ * (same points, same estimator), sharing one basis and dtype.  Paths of all
+ * options are generated in one launch; the backward sweeps run in one
+ * persistent launch in which workgroups claim (option, tile) slots and each
+ * option synchronises only its own tiles, so options of uneven path and date
+ * counts overlap on the device.  Each option's result depends only on its own
+ * data (fixed-order reductions): the same alone and in any mix.  h_out
+ * (2 * n_opts doubles, or NULL to return after enqueueing) receives price
+ * and std_err per option in the caller's order.  Fails with AM_EDIM if one
+ * option needs more tiles than the device holds resident. */
+int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                   void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out);
+
 /* Thread-local description of the last failure on this thread; valid until
  * the next call on the same thread.  Never NULL. */
 const char *am_last_error(void);
@@ -181,6 +210,12 @@ int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left,
  * disabling also clears it. */
 int am_profile_enable(int32_t on);
 int am_profile_read(double ms[2], int64_t *calls);
+
+/* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 4
+ * or 16, FP64: 2 or 8; 0 restores the default).  Results of one option are
+ * identical for a given choice; different choices change the reduction
+ * order (differences at rounding level). */
+void am_debug_set_batch_ppt(int32_t ppt);
 
 /* Test hook: bound the device-side barrier waits of subsequent calls on this
  * thread to `spins` polls (0 restores the default).  A wait that runs out

@@ -46,6 +46,11 @@ class am_basis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32)]
 
 
+class am_option(ctypes.Structure):
+    _fields_ = [("params", am_params), ("n_paths", ctypes.c_int64), ("n_dates", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 def make_params(S0, K, r, sigma, T, is_call=False, allow_exercise=True) -> am_params:
     return am_params(float(S0), float(K), float(r), float(sigma), float(T),
                      int(bool(is_call)), int(bool(allow_exercise)))
@@ -92,6 +97,13 @@ def lib():
         L.am_price_paper_estimator.argtypes = [P(am_params), i64, i32, i32, ctypes.c_void_p, sz,
                                                ctypes.c_void_p, P(dbl)]
         L.am_price_paper_estimator.restype = ctypes.c_int
+        L.am_batch_workspace_bytes.argtypes = [P(am_option), i32, am_basis, i32]
+        L.am_batch_workspace_bytes.restype = sz
+        L.am_price_batch.argtypes = [P(am_option), i32, am_basis, i32, ctypes.c_void_p, sz,
+                                     ctypes.c_void_p, P(dbl)]
+        L.am_price_batch.restype = ctypes.c_int
+        L.am_debug_set_batch_ppt.argtypes = [i32]
+        L.am_debug_set_batch_ppt.restype = None
         L.am_last_error.argtypes = []
         L.am_last_error.restype = ctypes.c_char_p
         L.am_max_dates.argtypes = []
@@ -204,6 +216,44 @@ def am_price_paper_estimator(params: am_params, n_paths: int, n_points: int, dty
     return None
 
 
+def make_options(specs) -> "ctypes.Array":
+    """specs: iterable of dicts with S0, K, r, sigma, T, n_paths, n_dates
+    (is_call, allow_exercise optional)."""
+    specs = list(specs)
+    arr = (am_option * len(specs))()
+    for i, d in enumerate(specs):
+        arr[i].params = make_params(d["S0"], d["K"], d["r"], d["sigma"], d["T"],
+                                    d.get("is_call", False), d.get("allow_exercise", True))
+        arr[i].n_paths = int(d["n_paths"])
+        arr[i].n_dates = int(d["n_dates"])
+        arr[i].reserved = 0
+    return arr
+
+
+def am_batch_workspace_bytes(opts, basis: am_basis, dtype) -> int:
+    return int(lib().am_batch_workspace_bytes(opts, len(opts), basis, _dtype(dtype)))
+
+
+def am_price_batch(opts, basis: am_basis, dtype, workspace, stream=None, wait: bool = True):
+    """Price a batch (am_option array) in two launches; returns an [n][2]
+    numpy array of (price, std_err) or None when wait=False."""
+    import numpy as np
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    n = len(opts)
+    out = (ctypes.c_double * (2 * n))() if wait else None
+    _check(lib().am_price_batch(opts, n, basis, _dtype(dtype), ctypes.c_void_p(workspace.data_ptr()),
+                                workspace.numel(), ctypes.c_void_p(stream.cuda_stream), out))
+    if wait:
+        return np.frombuffer(out, dtype=np.float64).reshape(n, 2).copy()
+    return None
+
+
+def am_debug_set_batch_ppt(ppt: int) -> None:
+    lib().am_debug_set_batch_ppt(int(ppt))
+
+
 def am_last_error() -> str:
     return lib().am_last_error().decode()
 
@@ -288,6 +338,13 @@ class Pricer:
         nbytes = am_workspace_bytes(n_paths, n_dates, basis, dtype)
         ws = self.workspace(nbytes)
         return am_price_american_rqmc(params, n_paths, n_dates, basis, dtype, shifts, ws, self.stream)
+
+    def price_batch(self, opts, basis: am_basis, dtype, wait: bool = True):
+        nbytes = am_batch_workspace_bytes(opts, basis, dtype)
+        if nbytes == 0:
+            raise AmError(AM_EINVAL, am_last_error())
+        ws = self.workspace(nbytes)
+        return am_price_batch(opts, basis, dtype, ws, self.stream, wait)
 
     def price_paper(self, params: am_params, n_paths: int, n_points: int, dtype, wait: bool = True):
         nbytes = am_workspace_bytes(n_paths, n_points, make_basis("monomial", 0), dtype)

@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -25,6 +26,7 @@ namespace {
 
 thread_local std::string g_err = "no error";
 thread_local uint32_t g_spin_limit = 0;
+thread_local int32_t g_batch_ppt = 0;   // batch tile choice (0 = default or tuned)
 constexpr uint32_t kDefaultSpin = 1u << 22;
 
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
@@ -316,6 +318,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     sa.rec = (double *)(ws + L.off_rec);
     sa.result = (double *)(ws + L.off_result);
     sa.sync = (uint32_t *)(ws + L.off_result + 64);
+    sa.err = sa.sync + 2;
     sa.datec = (const amq::DateConst *)(ws + L.off_datec);
     sa.N = N; sa.ld = L.ld;
     sa.M = M; sa.G = plan.G;
@@ -482,6 +485,77 @@ int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_d
     return AM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    std::vector<int> order;                       // options by decreasing work
+    std::vector<int64_t> ld, offS, offPV;
+    std::vector<size_t> offDatec, offRec;
+    std::vector<int32_t> G, tile_base;
+    size_t off_part = 0, off_res = 0, off_sync = 0, off_gsync = 0, off_desc = 0, off_tiles = 0,
+           off_units = 0, total = 0;
+    int total_tiles = 0, max_M = 0;
+    int64_t total_blocks = 0, max_units = 0;
+};
+
+constexpr int64_t kBatchTileAlign = 4096;   // rows padded to a multiple of every batch tile
+
+int batch_plan(const am_option *opts, int32_t n, int32_t dtype, BatchPlan &P)
+{
+    const size_t s = dtype == AM_FP64 ? 8 : 4;
+    P.order.resize(n);
+    for (int i = 0; i < n; ++i) P.order[i] = i;
+    std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) {
+        const double wa = (double)opts[a].n_paths * opts[a].n_dates;
+        const double wb = (double)opts[b].n_paths * opts[b].n_dates;
+        return wa > wb;
+    });
+    P.ld.assign(n, 0); P.offS.assign(n, 0); P.offPV.assign(n, 0);
+    P.offDatec.assign(n, 0); P.offRec.assign(n, 0); P.G.assign(n, 0); P.tile_base.assign(n, 0);
+    size_t o = 0;
+    int tiles = 0;
+    for (int q = 0; q < n; ++q) {
+        const int i = P.order[q];
+        const int64_t ld = (opts[i].n_paths + kBatchTileAlign - 1) / kBatchTileAlign * kBatchTileAlign;
+        P.ld[i] = ld;
+        P.offS[i] = (int64_t)o;  o = align256(o + (size_t)opts[i].n_dates * ld * s);
+        P.offPV[i] = (int64_t)o; o = align256(o + (size_t)ld * s);
+        P.tile_base[i] = tiles;
+        P.total_blocks += ld / 64;
+        P.max_units += (ld / 64 + amq::kWaves - 1) / amq::kWaves;
+        if (opts[i].n_dates > P.max_M) P.max_M = opts[i].n_dates;
+    }
+    for (int q = 0; q < n; ++q) {
+        const int i = P.order[q];
+        P.offDatec[i] = o; o = align256(o + (size_t)(opts[i].n_dates + 1) * sizeof(amq::DateConst));
+        P.offRec[i] = o;   o = align256(o + (size_t)(opts[i].n_dates + 1) * amq::kRec * 8);
+    }
+    P.off_res = o;   o = align256(o + (size_t)n * 8 * 8);
+    P.off_sync = o;  o = align256(o + (size_t)n * 16 * 4);
+    P.off_gsync = o; o = align256(o + 16 * 4);
+    P.off_desc = o;  o = align256(o + (size_t)n * sizeof(amq::BatchOpt));
+    // tiles: the smallest batch tile (256 paths) bounds the count from above
+    int64_t max_tiles = 0;
+    for (int i = 0; i < n; ++i) max_tiles += P.ld[i] / 256;
+    P.off_tiles = o; o = align256(o + (size_t)max_tiles * 4);
+    P.off_part = o;  o = align256(o + (size_t)max_tiles * amq::kPartStride * 8);
+    P.off_units = o; o = align256(o + (size_t)P.max_units * sizeof(amq::GenUnit));
+    P.total = o;
+    (void)tiles;
+    return AM_OK;
+}
+
+int validate_batch(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
+{
+    if (!opts || n < 1) return fail(AM_EINVAL, "need at least one option");
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(&opts[i].params, opts[i].n_paths, opts[i].n_dates, basis, dtype);
+        if (rc) return fail(rc, "option %d: %s", i, g_err.c_str());
+    }
+    return AM_OK;
+}
+
 int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n_points,
                              int32_t dtype, void *d_workspace, size_t ws_bytes, void *hip_stream,
                              double *h_out)
@@ -531,6 +605,136 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
     if (!h_out) return AM_OK;
     return fetch_result(ws, L, stream, h_out);
 }
+
+size_t am_batch_workspace_bytes(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype)
+{
+    if (validate_batch(opts, n_opts, basis, dtype)) return 0;
+    BatchPlan P;
+    batch_plan(opts, n_opts, dtype, P);
+    return P.total;
+}
+
+int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                   void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out)
+{
+    int rc = validate_batch(opts, n_opts, basis, dtype);
+    if (rc) return rc;
+    BatchPlan P;
+    batch_plan(opts, n_opts, dtype, P);
+    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    const int fp64 = dtype == AM_FP64;
+    const int ppt = g_batch_ppt ? g_batch_ppt : (fp64 ? 8 : 16);
+    const int64_t tile = (int64_t)amq::kWG * ppt;
+    if (kBatchTileAlign % tile != 0) return fail(AM_EINVAL, "batch tile %lld does not divide the row padding", (long long)tile);
+    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, ppt, basis.degree);
+    if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel for ppt %d degree %d", ppt, basis.degree);
+    const int capacity = per_cu * st->num_cu;
+    char *ws = (char *)d_workspace;
+    hipStream_t stream = (hipStream_t)hip_stream;
+
+    std::vector<amq::BatchOpt> desc(n_opts);
+    std::vector<int32_t> tile_opt;
+    int max_G = 0;
+    int tiles = 0;
+    for (int q = 0; q < n_opts; ++q) {
+        const int i = P.order[q];
+        const am_option &op = opts[i];
+        const amq::BridgeNode *sched = nullptr;
+        rc = get_schedule(st, op.n_dates, &sched);
+        if (rc) return rc;
+        amq::BatchOpt &d = desc[i];
+        memset(&d, 0, sizeof d);
+        d.S = ws + P.offS[i];
+        d.pv = ws + P.offPV[i];
+        d.sched = sched;
+        d.datec = (amq::DateConst *)(ws + P.offDatec[i]);
+        d.rec = (double *)(ws + P.offRec[i]);
+        d.result = (double *)(ws + P.off_res) + (size_t)i * 8;
+        d.sync = (uint32_t *)(ws + P.off_sync) + (size_t)i * 16;
+        d.N = op.n_paths;
+        d.ld = P.ld[i];
+        d.M = op.n_dates;
+        d.G = (int32_t)((op.n_paths + tile - 1) / tile);
+        d.tile_base = tiles;
+        d.is_call = op.params.is_call;
+        d.allow_exercise = op.params.allow_exercise;
+        d.S0 = op.params.S0; d.K = op.params.K; d.r = op.params.r; d.sigma = op.params.sigma;
+        d.T = op.params.T;
+        const double dt = op.params.T / (double)op.n_dates;
+        d.mu = (op.params.r - 0.5 * op.params.sigma * op.params.sigma) * dt;
+        d.vol = op.params.sigma * sqrt(dt);
+        for (int g = 0; g < d.G; ++g) tile_opt.push_back(i);
+        tiles += d.G;
+        if (d.G > max_G) max_G = d.G;
+    }
+    const int grid = tiles < capacity ? tiles : capacity;
+    if (max_G > grid)
+        return fail(AM_EDIM, "an option needs %d tiles but only %d workgroups are resident", max_G, grid);
+    // generation units: waves of R blocks, about 32 waves per CU in total
+    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    int64_t R = (P.total_blocks + target_waves - 1) / target_waves;
+    if (R < 1) R = 1;
+    std::vector<amq::GenUnit> units;
+    for (int q = 0; q < n_opts; ++q) {
+        const int i = P.order[q];
+        const int64_t nb = P.ld[i] / 64;
+        for (int64_t b = 0; b < nb; b += amq::kWaves * R) {
+            amq::GenUnit u;
+            u.opt = i; u.pad = 0; u.b0 = b; u.b1 = b + amq::kWaves * R < nb ? b + amq::kWaves * R : nb;
+            units.push_back(u);
+        }
+    }
+    if ((int64_t)units.size() > P.max_units) return fail(AM_EDEVICE, "unit table overflow");
+    HIP_TRY(hipMemcpyAsync(ws + P.off_desc, desc.data(), desc.size() * sizeof(amq::BatchOpt),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws + P.off_tiles, tile_opt.data(), tile_opt.size() * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws + P.off_units, units.data(), units.size() * sizeof(amq::GenUnit),
+                           hipMemcpyHostToDevice, stream));
+    uint32_t *gsync = (uint32_t *)(ws + P.off_gsync);
+    ProfRec *pr = nullptr;
+    if (g_prof.on) {
+        rc = prof_slot(&pr);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(pr->e[0], stream));
+    }
+    HIP_TRY(amq::launch_generate_batch((const amq::BatchOpt *)(ws + P.off_desc),
+                                       (const amq::GenUnit *)(ws + P.off_units), (int)units.size(),
+                                       st->d_V, gsync, P.max_M, fp64, stream));
+    if (pr) HIP_TRY(hipEventRecord(pr->e[1], stream));
+    amq::BatchGlobal g;
+    memset(&g, 0, sizeof g);
+    g.part = (double *)(ws + P.off_part);
+    g.claim = gsync;
+    g.err = gsync + 1;
+    g.total_tiles = tiles;
+    g.laguerre = basis.kind == AM_BASIS_LAGUERRE;
+    g.spin_limit = g_spin_limit ? g_spin_limit : kDefaultSpin;
+    hipError_t e = amq::launch_sweep_batch((const amq::BatchOpt *)(ws + P.off_desc),
+                                           (const int32_t *)(ws + P.off_tiles), g, grid, fp64, ppt,
+                                           basis.degree, stream);
+    if (e != hipSuccess)
+        return fail(AM_EDEVICE, "batch sweep launch (grid %d, ppt %d) failed: %s", grid, ppt, hipGetErrorString(e));
+    if (pr) HIP_TRY(hipEventRecord(pr->e[2], stream));
+    if (!h_out) return AM_OK;
+    std::vector<double> res((size_t)n_opts * 8);
+    uint32_t gs[16];
+    HIP_TRY(hipMemcpyAsync(res.data(), ws + P.off_res, res.size() * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(gs, gsync, sizeof gs, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (gs[1] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
+    for (int i = 0; i < n_opts; ++i) {
+        h_out[2 * i] = res[(size_t)i * 8];
+        h_out[2 * i + 1] = res[(size_t)i * 8 + 1];
+        if (!isfinite(h_out[2 * i])) return fail(AM_EDEVICE, "option %d: non-finite result", i);
+    }
+    return AM_OK;
+}
+
+void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
 
 int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left, int32_t *right,
                       double *wl, double *wr, double *sd)

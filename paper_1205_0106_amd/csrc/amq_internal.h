@@ -61,7 +61,8 @@ struct SweepArgs {
     double *part;             // [kMaxGroups][kPartStride]
     double *rec;              // [M+1][kRec]
     double *result;           // [8]
-    uint32_t *sync;           // [0] arrivals, [1] released epoch, [2] error
+    uint32_t *sync;           // [0] arrivals, [1] released epoch
+    uint32_t *err;            // error word: a wait ran out (every group exits)
     const DateConst *datec;   // [M+1]
     int64_t N, ld;
     int32_t M, G;
@@ -83,6 +84,36 @@ struct PaperArgs {
     double K, r, sigma, dt;
 };
 
+// One option of a batch, as the kernels see it (all pointers into the
+// caller's workspace or the library's schedule cache).
+struct alignas(64) BatchOpt {
+    void *S;                  // [M][ld] T
+    void *pv;                 // [ld] T
+    const BridgeNode *sched;  // [M]
+    DateConst *datec;         // [M+1]
+    double *rec;              // [M+1][kRec]
+    double *result;           // [8]
+    uint32_t *sync;           // [16] barrier words of this option
+    int64_t N, ld;
+    int32_t M, G;             // dates, tiles
+    int32_t tile_base;        // first partial slot / global tile index
+    int32_t is_call, allow_exercise, pad;
+    double S0, K, r, sigma, T, mu, vol;
+};
+
+struct GenUnit {              // one generation workgroup: blocks [b0, b1) of option opt
+    int32_t opt, pad;
+    int64_t b0, b1;
+};
+
+struct BatchGlobal {
+    double *part;             // [total tiles][kPartStride]
+    uint32_t *claim;          // tile claim counter (zeroed by generation)
+    uint32_t *err;            // error word (zeroed by generation)
+    int32_t total_tiles, laguerre;
+    uint32_t spin_limit, pad;
+};
+
 // Launchers (defined with the kernels).
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s);
 // Returns hipErrorInvalidValue if no kernel exists for (fp64, ppt, degree).
@@ -91,5 +122,11 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s);
 int sweep_blocks_per_cu(int fp64, int ppt, int degree);
 size_t generate_lds_bytes(int M);
 hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
+hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
+                                 const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
+                                 hipStream_t s);
+hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
+                              int grid, int fp64, int ppt, int degree, hipStream_t s);
+int sweep_batch_blocks_per_cu(int fp64, int ppt, int degree);
 
 }  // namespace amq

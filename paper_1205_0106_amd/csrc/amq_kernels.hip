@@ -174,10 +174,14 @@ size_t generate_lds_bytes(int M)
 // log2(M) + 2 live values; dimension order follows the breadth-first node
 // numbering, which only changes the order the Sobol dimensions are read.
 // ---------------------------------------------------------------------------
+// One workgroup's share: `init` (the group holding the option's first block)
+// writes the option's date constants and clears its barrier words; wave
+// blocks [w0, w1) are generated.
 template <typename T, int WHAT, bool MID>
-__global__ void __launch_bounds__(kWG)
-gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
-           const uint32_t *__restrict__ shift)
+__device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__restrict__ V,
+                                         const BridgeNode *__restrict__ sched,
+                                         const uint32_t *__restrict__ shift, bool init, int64_t w0,
+                                         int64_t w1)
 {
     extern __shared__ uint32_t lds[];
     const int M = a.M;
@@ -185,7 +189,7 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
     uint32_t *ttab = lds;                                   // [M][16]
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
 
-    if (blockIdx.x == 0 && WHAT == 0) {
+    if (init && WHAT == 0) {
         if (tid < 16) a.sync[tid] = 0u;
         for (int k = tid; k <= M; k += kWG) {
             const double tk = (double)k * a.T / (double)M;
@@ -210,9 +214,6 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
         ttab[e] = t;
     }
 
-    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
-    const int64_t w0 = gw * a.R;
-    const int64_t w1 = min(w0 + (int64_t)a.R, a.nblocks);
     if (w0 < w1) {
         const uint64_t n0 = (uint64_t)w0 << 6;
         const uint64_t g0 = n0 ^ (n0 >> 1);
@@ -295,6 +296,17 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
     }
 }
 
+template <typename T, int WHAT, bool MID>
+__global__ void __launch_bounds__(kWG)
+gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
+           const uint32_t *__restrict__ shift)
+{
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t w0 = gw * a.R;
+    const int64_t w1 = min(w0 + (int64_t)a.R, a.nblocks);
+    gen_body<T, WHAT, MID>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
+}
+
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
 {
     const int64_t waves = (a.nblocks + a.R - 1) / a.R;
@@ -330,14 +342,15 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 only.  Returns false if the wait was abandoned.
-__device__ bool wait_release(uint32_t *sync, uint32_t epoch, uint32_t limit)
+// Thread 0 only.  Returns false if the wait was abandoned (this wait ran out,
+// or another did and raised the error word `err`).
+__device__ bool wait_release(uint32_t *sync, uint32_t *err, uint32_t epoch, uint32_t limit)
 {
     uint32_t it = 0;
     while (ld_agent(sync + 1) < epoch) {
-        if (ld_agent(sync + 2) != 0u) return false;
+        if (ld_agent(err) != 0u) return false;
         if (++it > limit) {
-            __hip_atomic_store(sync + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
         __builtin_amdgcn_s_sleep(2);
@@ -373,11 +386,11 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 // Publish this group's partial sums and arrive.  Returns (in every thread)
 // whether this group arrived last for barrier `epoch`.
 template <int NV>
-__device__ bool arrive(const double (&v)[NV], double *part, uint32_t *sync, uint32_t epoch,
-                       uint32_t G, int *s_flag)
+__device__ bool arrive(const double (&v)[NV], double *part, uint32_t gid, uint32_t *sync,
+                       uint32_t epoch, uint32_t G, int *s_flag)
 {
     if (threadIdx.x == 0) {
-        double *dst = part + (size_t)blockIdx.x * kPartStride;
+        double *dst = part + (size_t)gid * kPartStride;
 #pragma unroll
         for (int q = 0; q < NV; ++q) dst[q] = v[q];
         const uint32_t old = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -573,8 +586,8 @@ __device__ __forceinline__ T exercise_update(T s, T pvj, bool valid, T K, bool c
 // paths are never in the money and keep pv = 0: no bounds checks.
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, int D>
-__device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t e0,
-                                           T (&pv)[PPT], uint32_t &epoch, bool &alive,
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
+                                           uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                            double (*s_red)[32], double (*s_red8)[32], double *s_tot,
                                            double (*s_L)[8], double *s_w, double *s_beta, int *s_flag)
 {
@@ -583,7 +596,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     constexpr bool KEEP = SH::KEEP;
     constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
     constexpr int NV = NA + NB + 1;
-    constexpr int BLK = sizeof(T) == 4 ? 8 : PPT;    // binary32 block length (paths)
+    // binary32 block length (paths); it must divide PPT so every block is flushed
+    constexpr int BLK = sizeof(T) == 4 ? (PPT < 8 ? PPT : 8) : PPT;
+    static_assert(PPT % BLK == 0, "block length must divide the paths per thread");
     constexpr uint32_t JS = 64 * VW;                 // element stride between a lane's vectors
 
     const int tid = threadIdx.x;
@@ -593,7 +608,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     const bool lag = a.laguerre != 0;
     const T wc = sizeof(T) == 4 ? (T)(-1.4426950408889634 / (2.0 * a.K)) : (T)(-0.5 / a.K);
     const uint32_t G = (uint32_t)a.G;
-    const int64_t tile0 = (int64_t)blockIdx.x * kWG * PPT;
+    const int64_t tile0 = (int64_t)gid * kWG * PPT;
     const uint32_t voff = (e0 - (uint32_t)tile0) * (uint32_t)sizeof(T);   // byte offset in the tile
     constexpr int32_t kTileBytes = kWG * PPT * (int32_t)sizeof(T);
     // Buffer loads: tile base in SGPRs, one lane offset, constant per-vector
@@ -670,7 +685,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 
         group_sum<NV>(acc, s_red);
         ++epoch;
-        const bool last = arrive<NV>(acc, a.part, a.sync, epoch, G, s_flag);
+        const bool last = arrive<NV>(acc, a.part, gid, a.sync, epoch, G, s_flag);
 
         if (KEEP && k >= 2) {
             const T *nrow = S + (size_t)(k - 2) * ld;
@@ -687,7 +702,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
             }
         }
         if (tid == 0) {
-            const bool okw = wait_release(a.sync, epoch, a.spin_limit);
+            const bool okw = wait_release(a.sync, a.err, epoch, a.spin_limit);
             s_flag[1] = okw ? 1 : 0;
             if (okw) {
                 const double *rec = a.rec + (size_t)k * kRec;
@@ -739,35 +754,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     }
 }
 
-template <typename T, int PPT, int D>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
-sweep_kernel(SweepArgs a, const T *__restrict__ S)
+// Epilogue (eqs. (6)-(8)): FP64 sums of the discounted cashflows and their
+// squares through one more barrier; the last group writes the result.
+template <typename T, int PPT>
+__device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, uint32_t e0,
+                                            const T (&pv)[PPT], uint32_t epoch, double (*s_red)[32],
+                                            double (*s_red8)[32], double *s_tot, int *s_flag)
 {
-    using SH = SweepShape<T, PPT>;
-    constexpr int VW = SH::VW, NVEC = SH::NVEC;
+    constexpr int VW = 16 / sizeof(T), NVEC = PPT / VW;
     constexpr uint32_t JS = 64 * VW;
-    static_assert(PPT % VW == 0, "PPT must be a multiple of the vector width");
-
-    __shared__ double s_red[kWaves][32];
-    __shared__ double s_red8[8][32];
-    __shared__ double s_tot[32];
-    __shared__ double s_L[8][8];
-    __shared__ double s_w[24];
-    __shared__ double s_beta[10];
-    __shared__ int s_flag[2];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int64_t N = a.N;
-    const int64_t tile0 = (int64_t)blockIdx.x * kWG * PPT;
-    const uint32_t e0 = (uint32_t)(tile0 + (int64_t)wave * 64 * PPT + lane * VW);
-
-    T pv[PPT];
-    uint32_t epoch = 0;
-    bool alive = true;
-    sweep_body<T, PPT, D>(a, S, e0, pv, epoch, alive, s_red, s_red8, s_tot, s_L, s_w, s_beta, s_flag);
-    if (!alive) return;
-
-    // eqs. (6)-(8): FP64 sum of discounted cashflows and of their squares
     double fin[2] = {0.0, 0.0};
     T *pvo = (T *)a.pv_out;
 #pragma unroll
@@ -785,7 +782,7 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
     group_sum<2>(fin, s_red);
     ++epoch;
     const uint32_t G = (uint32_t)a.G;
-    const bool last = arrive<2>(fin, a.part, a.sync, epoch, G, s_flag);
+    const bool last = arrive<2>(fin, a.part, gid, a.sync, epoch, G, s_flag);
     if (last) {
         reduce_partials<2>(a.part, G, s_tot, s_red8);
         if (tid == 0) {
@@ -813,17 +810,48 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
                 // visible (stream order); the last replicate aggregates
                 a.rep_out[a.rep] = price;
                 if (a.rep + 1 == a.n_rep) {
-                    double s1 = 0.0;
-                    for (int q = 0; q < a.n_rep; ++q) s1 += a.rep_out[q];
-                    const double m = s1 / (double)a.n_rep;
-                    double s2 = 0.0;
-                    for (int q = 0; q < a.n_rep; ++q) s2 += (a.rep_out[q] - m) * (a.rep_out[q] - m);
+                    double s1r = 0.0;
+                    for (int q = 0; q < a.n_rep; ++q) s1r += a.rep_out[q];
+                    const double m = s1r / (double)a.n_rep;
+                    double s2r = 0.0;
+                    for (int q = 0; q < a.n_rep; ++q) s2r += (a.rep_out[q] - m) * (a.rep_out[q] - m);
                     a.result[0] = m;
-                    a.result[1] = a.n_rep > 1 ? sqrt(s2 / (double)(a.n_rep - 1) / (double)a.n_rep) : 0.0;
+                    a.result[1] = a.n_rep > 1 ? sqrt(s2r / (double)(a.n_rep - 1) / (double)a.n_rep) : 0.0;
                 }
             }
         }
     }
+}
+
+template <typename T, int PPT>
+__device__ __forceinline__ uint32_t tile_e0(uint32_t gid)
+{
+    constexpr int VW = 16 / sizeof(T);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    return (uint32_t)((int64_t)gid * kWG * PPT + (int64_t)wave * 64 * PPT + lane * VW);
+}
+
+template <typename T, int PPT, int D>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+sweep_kernel(SweepArgs a, const T *__restrict__ S)
+{
+    static_assert(PPT % (16 / sizeof(T)) == 0, "PPT must be a multiple of the vector width");
+    __shared__ double s_red[kWaves][32];
+    __shared__ double s_red8[8][32];
+    __shared__ double s_tot[32];
+    __shared__ double s_L[8][8];
+    __shared__ double s_w[24];
+    __shared__ double s_beta[10];
+    __shared__ int s_flag[2];
+
+    const uint32_t gid = blockIdx.x;
+    const uint32_t e0 = tile_e0<T, PPT>(gid);
+    T pv[PPT];
+    uint32_t epoch = 0;
+    bool alive = true;
+    sweep_body<T, PPT, D>(a, S, gid, e0, pv, epoch, alive, s_red, s_red8, s_tot, s_L, s_w, s_beta, s_flag);
+    if (!alive) return;
+    sweep_final<T, PPT>(a, gid, e0, pv, epoch, s_red, s_red8, s_tot, s_flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,6 +909,173 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
     const void *Sp = a.S;
     void *params[] = {(void *)&args, (void *)&Sp};
     return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3(kWG), params, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many options with uneven path and date counts in two launches.
+//
+// Generation: each workgroup owns a block range of one option (unit table
+// built on the host).  Sweep: one cooperative persistent grid; workgroups
+// claim (option, tile) slots from a global counter in a fixed order (options
+// by decreasing work, each option's tiles contiguous), run that tile through
+// all of the option's dates with the option's own barrier words and partial
+// slots, then claim again.  Claims are in order, so at most one option is
+// partly claimed at any time and every earlier option can finish; with each
+// option needing no more tiles than the grid holds, every claimed tile is
+// eventually joined by the rest of its option.  An option's result depends
+// only on its own tiles and the fixed reduction order, not on which group ran
+// which tile, so it is the same alone and in any mix.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t *V)
+{
+    GenArgs a;
+    a.S = o.S;
+    a.V = V;
+    a.sched = o.sched;
+    a.datec = o.datec;
+    a.sync = o.sync;
+    a.N = o.N;
+    a.ld = o.ld;
+    a.nblocks = o.ld / 64;
+    a.M = o.M;
+    a.R = 1;
+    a.what = 0;
+    a.pad = 0;
+    a.S0 = o.S0; a.K = o.K; a.r = o.r; a.sigma = o.sigma; a.T = o.T;
+    a.mu = o.mu; a.vol = o.vol;
+    a.shift = nullptr;
+    return a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG)
+gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ units,
+                 const uint32_t *__restrict__ V, uint32_t *gsync)
+{
+    const GenUnit u = units[blockIdx.x];
+    const BatchOpt o = opts[u.opt];
+    if (blockIdx.x == 0 && threadIdx.x < 16) gsync[threadIdx.x] = 0u;
+    const GenArgs a = gen_args_of(o, V);
+    const int64_t per = (u.b1 - u.b0 + kWaves - 1) / kWaves;
+    const int64_t w0 = u.b0 + (int64_t)(threadIdx.x >> 6) * per;
+    const int64_t w1 = min(w0 + per, u.b1);
+    gen_body<T, 0, false>(a, V, o.sched, nullptr, u.b0 == 0, w0, w1);
+}
+
+template <typename T, int PPT, int D>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict__ tile_opt,
+                   BatchGlobal g)
+{
+    __shared__ double s_red[kWaves][32];
+    __shared__ double s_red8[8][32];
+    __shared__ double s_tot[32];
+    __shared__ double s_L[8][8];
+    __shared__ double s_w[24];
+    __shared__ double s_beta[10];
+    __shared__ int s_flag[2];
+    __shared__ int s_claim;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = (int)__hip_atomic_fetch_add(g.claim, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ld_agent(g.err) != 0u) t = g.total_tiles;
+            s_claim = t;
+        }
+        __syncthreads();
+        const int t = s_claim;
+        if (t >= g.total_tiles) return;
+        const BatchOpt o = opts[tile_opt[t]];
+        SweepArgs a;
+        a.S = o.S;
+        a.pv_out = o.pv;
+        a.part = g.part + (size_t)o.tile_base * kPartStride;
+        a.rec = o.rec;
+        a.result = o.result;
+        a.sync = o.sync;
+        a.err = g.err;
+        a.datec = o.datec;
+        a.N = o.N; a.ld = o.ld;
+        a.M = o.M; a.G = o.G;
+        a.is_call = o.is_call; a.allow_exercise = o.allow_exercise;
+        a.laguerre = g.laguerre; a.degree = D;
+        a.S0 = o.S0; a.K = o.K;
+        a.spin_limit = g.spin_limit;
+        a.pad = 0;
+        a.rep_out = nullptr; a.rep = 0; a.n_rep = 0;
+        const uint32_t gid = (uint32_t)(t - o.tile_base);
+        const uint32_t e0 = tile_e0<T, PPT>(gid);
+        T pv[PPT];
+        uint32_t epoch = 0;
+        bool alive = true;
+        sweep_body<T, PPT, D>(a, (const T *)o.S, gid, e0, pv, epoch, alive, s_red, s_red8, s_tot, s_L,
+                              s_w, s_beta, s_flag);
+        if (!alive) return;
+        sweep_final<T, PPT>(a, gid, e0, pv, epoch, s_red, s_red8, s_tot, s_flag);
+    }
+}
+
+template <typename T, int PPT>
+static const void *sweep_batch_fn(int degree)
+{
+    switch (degree) {
+    case 0: return (const void *)&sweep_batch_kernel<T, PPT, 0>;
+    case 1: return (const void *)&sweep_batch_kernel<T, PPT, 1>;
+    case 2: return (const void *)&sweep_batch_kernel<T, PPT, 2>;
+    case 3: return (const void *)&sweep_batch_kernel<T, PPT, 3>;
+    case 4: return (const void *)&sweep_batch_kernel<T, PPT, 4>;
+    case 5: return (const void *)&sweep_batch_kernel<T, PPT, 5>;
+    case 6: return (const void *)&sweep_batch_kernel<T, PPT, 6>;
+    default: return nullptr;
+    }
+}
+
+static const void *sweep_batch_lookup(int fp64, int ppt, int degree)
+{
+    if (fp64) {
+        switch (ppt) {
+        case 2: return sweep_batch_fn<double, 2>(degree);
+        case 8: return sweep_batch_fn<double, 8>(degree);
+        default: return nullptr;
+        }
+    }
+    switch (ppt) {
+    case 4: return sweep_batch_fn<float, 4>(degree);
+    case 16: return sweep_batch_fn<float, 16>(degree);
+    default: return nullptr;
+    }
+}
+
+int sweep_batch_blocks_per_cu(int fp64, int ppt, int degree)
+{
+    const void *f = sweep_batch_lookup(fp64, ppt, degree);
+    if (!f) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWG, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
+                                 const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
+                                 hipStream_t s)
+{
+    const size_t lds = generate_lds_bytes(max_dates);
+    if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
+    else      hipLaunchKernelGGL((gen_batch_kernel<float>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
+                              int grid, int fp64, int ppt, int degree, hipStream_t s)
+{
+    const void *f = sweep_batch_lookup(fp64, ppt, degree);
+    if (!f) return hipErrorInvalidValue;
+    const BatchOpt *o = opts;
+    const int32_t *to = tile_opt;
+    BatchGlobal gg = g;
+    void *params[] = {(void *)&o, (void *)&to, (void *)&gg};
+    return hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(kWG), params, 0, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,98 @@
+"""GPU parity of the batched path: many options with uneven path and date
+counts in one generation launch and one persistent sweep.  Each option must
+match the FP64 oracle to the single-option tolerance, and be bitwise the same
+priced alone (a batch of one) and in the mix."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1205_0106_amd.workloads import batch_options
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-4, "fp32": 2e-3}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def amq():
+    import torch
+    import paper_1205_0106_amd as amq
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    amq.lib()
+    return amq
+
+
+@pytest.fixture(scope="module")
+def pricer(amq):
+    return amq.Pricer(0)
+
+
+def _small_mix(n=24, seed=7):
+    # the batch workload's distribution, scaled down so the oracle is quick
+    return batch_options(n, seed=seed, log2_paths=(9.0, 13.0), dates=(3, 40))
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batch_matches_oracle(amq, orc, pricer, dtype):
+    specs = _small_mix()
+    opts = amq.make_options(specs)
+    b = amq.make_basis("monomial", 2)
+    log(f"  batch of {len(specs)} ({dtype})")
+    got = pricer.price_batch(opts, b, dtype)
+    worst = 0.0
+    for i, d in enumerate(specs):
+        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        err = abs(got[i, 0] - want.price)
+        worst = max(worst, err)
+        assert err <= TOL[dtype], (i, d, got[i], want.price)
+    log(f"    worst |gpu - oracle| = {worst:.3e}")
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batch_alone_equals_in_mix(amq, pricer, dtype):
+    specs = _small_mix(16, seed=11)
+    b = amq.make_basis("laguerre", 3)
+    mix = pricer.price_batch(amq.make_options(specs), b, dtype)
+    for i in (0, 5, 15):
+        alone = pricer.price_batch(amq.make_options([specs[i]]), b, dtype)
+        assert alone[0, 0] == mix[i, 0] and alone[0, 1] == mix[i, 1]
+    # and close to the single-option entry point (different tile shape)
+    p = amq.make_params(specs[3]["S0"], specs[3]["K"], specs[3]["r"], specs[3]["sigma"], specs[3]["T"],
+                        specs[3]["is_call"])
+    single = pricer.price(p, specs[3]["n_paths"], specs[3]["n_dates"], b, dtype)
+    assert abs(single[0] - mix[3, 0]) <= TOL[dtype]
+
+
+def test_batch_deterministic_and_tile_choice(amq, pricer):
+    specs = _small_mix(12, seed=3)
+    opts = amq.make_options(specs)
+    b = amq.make_basis("monomial", 3)
+    a = pricer.price_batch(opts, b, "fp32")
+    assert np.array_equal(a, pricer.price_batch(opts, b, "fp32"))
+    amq.am_debug_set_batch_ppt(4)
+    try:
+        c = pricer.price_batch(opts, b, "fp32")
+    finally:
+        amq.am_debug_set_batch_ppt(0)
+    assert np.abs(a - c)[:, 0].max() <= TOL["fp32"]
+
+
+def test_batch_full_distribution_sample(amq, orc, pricer):
+    # the batch workload's real size range on a seeded sample of 64 options
+    specs = batch_options(64)
+    opts = amq.make_options(specs)
+    b = amq.make_basis("monomial", 2)
+    got = pricer.price_batch(opts, b, "fp32")
+    for i in (0, 17, 63):
+        d = specs[i]
+        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        log(f"    opt {i}: N={d['n_paths']} M={d['n_dates']} gpu {got[i, 0]:.6f} oracle {want.price:.6f}")
+        assert abs(got[i, 0] - want.price) <= TOL["fp32"]

@@ -122,3 +122,16 @@ def test_binding_raises_when_library_missing(monkeypatch):
     monkeypatch.setattr(amq, "LIB_PATH", "/nonexistent/libamqmc.so")
     with pytest.raises(ImportError):
         amq.lib()
+
+
+def test_batch_workspace_sizing(amq):
+    from paper_1205_0106_amd.workloads import batch_options
+    specs = batch_options(32, seed=5)
+    opts = amq.make_options(specs)
+    b = amq.make_basis("monomial", 2)
+    n32 = amq.am_batch_workspace_bytes(opts, b, "fp32")
+    n64 = amq.am_batch_workspace_bytes(opts, b, "fp64")
+    need = sum(d["n_paths"] * d["n_dates"] for d in specs)
+    assert n32 >= 4 * need and n64 >= 8 * need and n64 > n32
+    bad = amq.make_options([dict(specs[0], sigma=-1.0)])
+    assert amq.am_batch_workspace_bytes(bad, b, "fp32") == 0
