@@ -211,6 +211,58 @@ int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left,
 int am_profile_enable(int32_t on);
 int am_profile_read(double ms[2], int64_t *calls);
 
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of pricing requests under an HBM budget.    */
+/* ---------------------------------------------------------------------- */
+typedef struct am_server am_server;
+
+typedef struct am_server_config {
+    size_t hbm_budget_bytes;       /* device pool allocated once; workspaces are carved from it */
+    double max_batch_path_steps;   /* cap on sum n_paths*n_dates per launched batch */
+    int32_t max_batch_requests;    /* cap on requests per launched batch */
+    int32_t n_streams;             /* batches in flight at once (1..8) */
+    am_basis basis;                /* shared by every request */
+    int32_t dtype;
+    int32_t reserved;
+} am_server_config;
+
+typedef struct am_result {
+    uint64_t request_id;
+    double price, std_err;
+    double t_arrival;              /* server clock (am_server_now), seconds */
+    double t_launch;               /* when its batch was enqueued */
+    double t_done;                 /* when completion was observed */
+    int32_t status;                /* AM_OK, AM_ENOMEM (larger than the budget), ... */
+    int32_t reserved;
+} am_result;
+
+/* Start a server on the current device: allocates the pool and starts a
+ * dispatcher thread.  Requests wait in arrival order; whenever a stream is
+ * free, the longest prefix of waiting requests whose batch workspace fits in
+ * the free pool (and under the batch caps) is launched as one batch
+ * (am_price_batch's kernels, persistent grid limited to 1/n_streams of the
+ * device so in-flight batches run side by side); completed batches return
+ * their memory.  Paths and cashflows stay resident in the pool until a
+ * request completes.  Results are those of am_price_batch, hence identical
+ * to pricing the request alone. */
+int am_server_create(const am_server_config *cfg, am_server **out);
+
+/* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now. */
+int am_server_submit(am_server *server, const am_option *opt, uint64_t request_id, double t_arrival);
+
+/* Move up to max_out completed results into out; *n_out receives the count. */
+int am_server_poll(am_server *server, am_result *out, int32_t max_out, int32_t *n_out);
+
+/* Server clock in seconds (monotonic). */
+double am_server_now(void);
+
+/* out: {batches launched, requests launched, path-steps launched, pool bytes in use}. */
+int am_server_stats(am_server *server, double out[4]);
+
+/* Finish every queued request, stop the dispatcher, free the pool.  Results
+ * not yet polled are discarded.  Returns the first fatal error, if any. */
+int am_server_destroy(am_server *server);
+
 /* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 4
  * or 16, FP64: 2 or 8; 0 restores the default).  Results of one option are
  * identical for a given choice; different choices change the reduction

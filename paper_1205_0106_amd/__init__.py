@@ -46,6 +46,19 @@ class am_basis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32)]
 
 
+class am_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_path_steps", ctypes.c_double),
+                ("max_batch_requests", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("basis", am_basis), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class am_result(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("price", ctypes.c_double),
+                ("std_err", ctypes.c_double), ("t_arrival", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class am_option(ctypes.Structure):
     _fields_ = [("params", am_params), ("n_paths", ctypes.c_int64), ("n_dates", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -102,6 +115,18 @@ def lib():
         L.am_price_batch.argtypes = [P(am_option), i32, am_basis, i32, ctypes.c_void_p, sz,
                                      ctypes.c_void_p, P(dbl)]
         L.am_price_batch.restype = ctypes.c_int
+        L.am_server_create.argtypes = [P(am_server_config), P(ctypes.c_void_p)]
+        L.am_server_create.restype = ctypes.c_int
+        L.am_server_submit.argtypes = [ctypes.c_void_p, P(am_option), ctypes.c_uint64, dbl]
+        L.am_server_submit.restype = ctypes.c_int
+        L.am_server_poll.argtypes = [ctypes.c_void_p, P(am_result), i32, P(i32)]
+        L.am_server_poll.restype = ctypes.c_int
+        L.am_server_now.argtypes = []
+        L.am_server_now.restype = dbl
+        L.am_server_stats.argtypes = [ctypes.c_void_p, P(dbl)]
+        L.am_server_stats.restype = ctypes.c_int
+        L.am_server_destroy.argtypes = [ctypes.c_void_p]
+        L.am_server_destroy.restype = ctypes.c_int
         L.am_debug_set_batch_ppt.argtypes = [i32]
         L.am_debug_set_batch_ppt.restype = None
         L.am_last_error.argtypes = []
@@ -248,6 +273,50 @@ def am_price_batch(opts, basis: am_basis, dtype, workspace, stream=None, wait: b
     if wait:
         return np.frombuffer(out, dtype=np.float64).reshape(n, 2).copy()
     return None
+
+
+class Server:
+    """Continuous-batching pricing server (am_server_* through the C-ABI)."""
+
+    def __init__(self, hbm_budget_bytes: int, basis: am_basis, dtype, *, n_streams: int = 2,
+                 max_batch_requests: int = 64, max_batch_path_steps: float = 2e9):
+        cfg = am_server_config(int(hbm_budget_bytes), float(max_batch_path_steps),
+                               int(max_batch_requests), int(n_streams), basis, _dtype(dtype), 0)
+        self._h = ctypes.c_void_p()
+        _check(lib().am_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._buf = (am_result * 1024)()
+
+    @staticmethod
+    def now() -> float:
+        return float(lib().am_server_now())
+
+    def submit(self, opt: "am_option", request_id: int, t_arrival: float = -1.0) -> None:
+        _check(lib().am_server_submit(self._h, ctypes.byref(opt), int(request_id), float(t_arrival)))
+
+    def poll(self):
+        n = ctypes.c_int32()
+        _check(lib().am_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(n)))
+        return [dict(id=r.request_id, price=r.price, std_err=r.std_err, t_arrival=r.t_arrival,
+                     t_launch=r.t_launch, t_done=r.t_done, status=r.status)
+                for r in self._buf[:n.value]]
+
+    def stats(self):
+        out = (ctypes.c_double * 4)()
+        _check(lib().am_server_stats(self._h, out))
+        return dict(batches=out[0], requests=out[1], path_steps=out[2], pool_bytes_used=out[3])
+
+    def close(self) -> None:
+        if self._h:
+            rc = lib().am_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
 
 def am_debug_set_batch_ppt(ppt: int) -> None:

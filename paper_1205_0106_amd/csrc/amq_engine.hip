@@ -12,7 +12,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <thread>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -614,27 +618,27 @@ size_t am_batch_workspace_bytes(const am_option *opts, int32_t n_opts, am_basis 
     return P.total;
 }
 
-int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
-                   void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out)
+}  // extern "C"
+
+namespace {
+
+// Enqueue one batch (generation + persistent sweep) on `stream`.  grid_cap
+// bounds the persistent grid (a fraction of the device when several batches
+// run side by side); cooperative selects hipLaunchCooperativeKernel.
+// staging (optional, pinned, staging_bytes) holds the uploaded tables.
+int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                  char *ws, const BatchPlan &P, hipStream_t stream, int grid_cap, bool cooperative,
+                  char *staging, size_t staging_bytes)
 {
-    int rc = validate_batch(opts, n_opts, basis, dtype);
-    if (rc) return rc;
-    BatchPlan P;
-    batch_plan(opts, n_opts, dtype, P);
-    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
-        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
-    DevState *st = nullptr;
-    rc = get_state(&st);
-    if (rc) return rc;
+    int rc = AM_OK;
     const int fp64 = dtype == AM_FP64;
     const int ppt = g_batch_ppt ? g_batch_ppt : (fp64 ? 8 : 16);
     const int64_t tile = (int64_t)amq::kWG * ppt;
     if (kBatchTileAlign % tile != 0) return fail(AM_EINVAL, "batch tile %lld does not divide the row padding", (long long)tile);
     const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, ppt, basis.degree);
     if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel for ppt %d degree %d", ppt, basis.degree);
-    const int capacity = per_cu * st->num_cu;
-    char *ws = (char *)d_workspace;
-    hipStream_t stream = (hipStream_t)hip_stream;
+    int capacity = per_cu * st->num_cu;
+    if (grid_cap > 0 && grid_cap < capacity) capacity = grid_cap;
 
     std::vector<amq::BatchOpt> desc(n_opts);
     std::vector<int32_t> tile_opt;
@@ -689,11 +693,20 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
         }
     }
     if ((int64_t)units.size() > P.max_units) return fail(AM_EDEVICE, "unit table overflow");
-    HIP_TRY(hipMemcpyAsync(ws + P.off_desc, desc.data(), desc.size() * sizeof(amq::BatchOpt),
-                           hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(ws + P.off_tiles, tile_opt.data(), tile_opt.size() * 4, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(ws + P.off_units, units.data(), units.size() * sizeof(amq::GenUnit),
-                           hipMemcpyHostToDevice, stream));
+    const size_t bd = desc.size() * sizeof(amq::BatchOpt), bt = tile_opt.size() * 4,
+                 bu = units.size() * sizeof(amq::GenUnit);
+    const void *src_d = desc.data(), *src_t = tile_opt.data(), *src_u = units.data();
+    if (staging && align256(bd) + align256(bt) + bu <= staging_bytes) {
+        memcpy(staging, desc.data(), bd);
+        memcpy(staging + align256(bd), tile_opt.data(), bt);
+        memcpy(staging + align256(bd) + align256(bt), units.data(), bu);
+        src_d = staging;
+        src_t = staging + align256(bd);
+        src_u = staging + align256(bd) + align256(bt);
+    }
+    HIP_TRY(hipMemcpyAsync(ws + P.off_desc, src_d, bd, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws + P.off_tiles, src_t, bt, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws + P.off_units, src_u, bu, hipMemcpyHostToDevice, stream));
     uint32_t *gsync = (uint32_t *)(ws + P.off_gsync);
     ProfRec *pr = nullptr;
     if (g_prof.on) {
@@ -715,15 +728,38 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
     g.spin_limit = g_spin_limit ? g_spin_limit : kDefaultSpin;
     hipError_t e = amq::launch_sweep_batch((const amq::BatchOpt *)(ws + P.off_desc),
                                            (const int32_t *)(ws + P.off_tiles), g, grid, fp64, ppt,
-                                           basis.degree, stream);
+                                           basis.degree, cooperative, stream);
     if (e != hipSuccess)
         return fail(AM_EDEVICE, "batch sweep launch (grid %d, ppt %d) failed: %s", grid, ppt, hipGetErrorString(e));
     if (pr) HIP_TRY(hipEventRecord(pr->e[2], stream));
+    return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                   void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out)
+{
+    int rc = validate_batch(opts, n_opts, basis, dtype);
+    if (rc) return rc;
+    BatchPlan P;
+    batch_plan(opts, n_opts, dtype, P);
+    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    char *ws = (char *)d_workspace;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    rc = enqueue_batch(st, opts, n_opts, basis, dtype, ws, P, stream, 0, true, nullptr, 0);
+    if (rc) return rc;
     if (!h_out) return AM_OK;
     std::vector<double> res((size_t)n_opts * 8);
     uint32_t gs[16];
     HIP_TRY(hipMemcpyAsync(res.data(), ws + P.off_res, res.size() * 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(gs, gsync, sizeof gs, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(gs, ws + P.off_gsync, sizeof gs, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (gs[1] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
     for (int i = 0; i < n_opts; ++i) {
@@ -735,6 +771,339 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
 }
 
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching under an HBM budget.
+// ---------------------------------------------------------------------------
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over one device pool (offsets in bytes, 256-aligned).
+struct PoolAlloc {
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t used = 0;
+    void init(size_t bytes) { free_.clear(); free_[0] = bytes; used = 0; }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t noff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                used += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align256(bytes);
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Request {
+    am_option opt;
+    uint64_t id;
+    double t_arrival;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char *staging = nullptr;          // pinned: uploaded tables
+    double *h_res = nullptr;          // pinned: [max][8] results + sync words
+    size_t staging_bytes = 0;
+    bool busy = false;
+    std::vector<Request> reqs;
+    size_t off = 0, bytes = 0;
+    double t_launch = 0.0;
+};
+
+}  // namespace
+
+struct am_server {
+    am_server_config cfg;
+    DevState *st = nullptr;
+    char *pool = nullptr;
+    PoolAlloc alloc;
+    std::vector<Slot> slots;
+    int grid_cap = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request> pending;
+    std::vector<am_result> done;
+    std::thread th;
+    bool stop = false;
+    int fatal = AM_OK;
+    std::string fatal_msg;
+    uint64_t n_batches = 0, n_requests = 0;
+    double busy_path_steps = 0.0;
+};
+
+namespace {
+
+void finish_slot(am_server *sv, Slot &sl, std::vector<am_result> &out)
+{
+    const uint32_t *gs = (const uint32_t *)(sl.h_res + (size_t)sl.reqs.size() * 8);
+    const double t = now_s();
+    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+        am_result r;
+        memset(&r, 0, sizeof r);
+        r.request_id = sl.reqs[i].id;
+        r.price = sl.h_res[i * 8];
+        r.std_err = sl.h_res[i * 8 + 1];
+        r.status = gs[1] != 0u ? AM_ETIMEOUT : (isfinite(r.price) ? AM_OK : AM_EDEVICE);
+        r.t_arrival = sl.reqs[i].t_arrival;
+        r.t_launch = sl.t_launch;
+        r.t_done = t;
+        out.push_back(r);
+    }
+    sv->alloc.release(sl.off, sl.bytes);
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
+// Launch the longest admissible prefix of the pending queue on slot `sl`.
+// Returns true if something was launched.
+bool launch_some(am_server *sv, Slot &sl, std::deque<Request> &pend, std::vector<am_result> &out)
+{
+    const am_server_config &c = sv->cfg;
+    std::vector<am_option> opts;
+    std::vector<Request> take;
+    double work = 0.0;
+    for (size_t i = 0; i < pend.size() && (int)take.size() < c.max_batch_requests; ++i) {
+        const double w = (double)pend[i].opt.n_paths * pend[i].opt.n_dates;
+        if (!take.empty() && work + w > c.max_batch_path_steps) break;
+        take.push_back(pend[i]);
+        opts.push_back(pend[i].opt);
+        work += w;
+    }
+    while (!take.empty()) {
+        BatchPlan P;
+        batch_plan(opts.data(), (int32_t)opts.size(), c.dtype, P);
+        size_t off = 0;
+        if (sv->alloc.alloc(P.total, &off)) {
+            sl.off = off;
+            sl.bytes = P.total;
+            sl.reqs = take;
+            sl.t_launch = now_s();
+            int rc = enqueue_batch(sv->st, opts.data(), (int32_t)opts.size(), c.basis, c.dtype,
+                                   sv->pool + off, P, sl.stream, sv->grid_cap, false, sl.staging,
+                                   sl.staging_bytes);
+            if (rc == AM_OK) {
+                char *ws = sv->pool + off;
+                rc = hipMemcpyAsync(sl.h_res, ws + P.off_res, opts.size() * 8 * 8, hipMemcpyDeviceToHost,
+                                    sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
+                if (rc == AM_OK)
+                    rc = hipMemcpyAsync(sl.h_res + opts.size() * 8, ws + P.off_gsync, 64,
+                                        hipMemcpyDeviceToHost, sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
+                if (rc == AM_OK)
+                    rc = hipEventRecord(sl.done, sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
+            }
+            if (rc != AM_OK) {
+                sv->alloc.release(off, P.total);
+                sv->fatal = rc;
+                sv->fatal_msg = g_err;
+                return false;
+            }
+            sl.busy = true;
+            for (size_t i = 0; i < take.size(); ++i) pend.pop_front();
+            sv->n_batches++;
+            sv->n_requests += take.size();
+            sv->busy_path_steps += work;
+            return true;
+        }
+        if (take.size() == 1) {
+            // a lone request that does not fit even an empty pool is refused
+            bool idle = sv->alloc.used == 0;
+            if (idle) {
+                am_result r;
+                memset(&r, 0, sizeof r);
+                r.request_id = take[0].id;
+                r.status = AM_ENOMEM;
+                r.t_arrival = take[0].t_arrival;
+                r.t_done = now_s();
+                out.push_back(r);
+                pend.pop_front();
+            }
+            return false;
+        }
+        work -= (double)take.back().opt.n_paths * take.back().opt.n_dates;
+        take.pop_back();
+        opts.pop_back();
+    }
+    return false;
+}
+
+void server_loop(am_server *sv)
+{
+    hipSetDevice(sv->st->dev);
+    std::deque<Request> local;
+    std::vector<am_result> out;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            while (!sv->pending.empty()) { local.push_back(sv->pending.front()); sv->pending.pop_front(); }
+            if (!out.empty()) { sv->done.insert(sv->done.end(), out.begin(), out.end()); out.clear(); }
+            bool any_busy = false;
+            for (auto &sl : sv->slots) any_busy = any_busy || sl.busy;
+            if (sv->stop && local.empty() && !any_busy) return;
+            if (sv->fatal != AM_OK && !any_busy) return;
+            if (local.empty() && !any_busy) {
+                sv->cv.wait_for(lk, std::chrono::microseconds(200));
+                continue;
+            }
+        }
+        bool progressed = false;
+        for (auto &sl : sv->slots) {
+            if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
+                finish_slot(sv, sl, out);
+                progressed = true;
+            }
+        }
+        if (sv->fatal == AM_OK) {
+            for (auto &sl : sv->slots) {
+                if (local.empty()) break;
+                if (!sl.busy && launch_some(sv, sl, local, out)) progressed = true;
+            }
+        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int am_server_create(const am_server_config *cfg, am_server **out)
+{
+    if (!cfg || !out) return fail(AM_EINVAL, "config and out must be non-NULL");
+    if (cfg->n_streams < 1 || cfg->n_streams > 8) return fail(AM_EINVAL, "n_streams must be in [1, 8]");
+    if (cfg->max_batch_requests < 1) return fail(AM_EINVAL, "max_batch_requests must be >= 1");
+    if (cfg->hbm_budget_bytes < (1u << 20)) return fail(AM_EINVAL, "hbm budget too small");
+    if (cfg->dtype != AM_FP64 && cfg->dtype != AM_FP32_BULK) return fail(AM_EINVAL, "unknown dtype");
+    if (cfg->basis.degree < 0 || cfg->basis.degree > AM_MAX_DEGREE) return fail(AM_EINVAL, "bad basis degree");
+    DevState *st = nullptr;
+    int rc = get_state(&st);
+    if (rc) return rc;
+    std::unique_ptr<am_server> sv(new am_server);
+    sv->cfg = *cfg;
+    sv->st = st;
+    if (hipMalloc((void **)&sv->pool, cfg->hbm_budget_bytes) != hipSuccess)
+        return fail(AM_ENOMEM, "hipMalloc of the %zu-byte serving pool failed", cfg->hbm_budget_bytes);
+    sv->alloc.init(cfg->hbm_budget_bytes);
+    const int fp64 = cfg->dtype == AM_FP64;
+    const int ppt = fp64 ? 8 : 16;
+    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, ppt, cfg->basis.degree);
+    if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel");
+    sv->grid_cap = per_cu * st->num_cu / cfg->n_streams;   // in-flight grids fit together
+    sv->slots.resize(cfg->n_streams);
+    for (auto &sl : sv->slots) {
+        HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+        sl.staging_bytes = 8u << 20;
+        if (hipHostMalloc((void **)&sl.staging, sl.staging_bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(AM_ENOMEM, "pinned staging allocation failed");
+        if (hipHostMalloc((void **)&sl.h_res, (size_t)cfg->max_batch_requests * 64 + 64, hipHostMallocDefault) != hipSuccess)
+            return fail(AM_ENOMEM, "pinned result allocation failed");
+    }
+    am_server *p = sv.release();
+    p->th = std::thread(server_loop, p);
+    *out = p;
+    return AM_OK;
+}
+
+int am_server_submit(am_server *sv, const am_option *opt, uint64_t request_id, double t_arrival)
+{
+    if (!sv || !opt) return fail(AM_EINVAL, "server and option must be non-NULL");
+    int rc = validate(&opt->params, opt->n_paths, opt->n_dates, sv->cfg.basis, sv->cfg.dtype);
+    if (rc) return rc;
+    Request r;
+    r.opt = *opt;
+    r.id = request_id;
+    r.t_arrival = t_arrival >= 0.0 ? t_arrival : now_s();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) return fail(AM_EINVAL, "server is stopping");
+        if (sv->fatal != AM_OK) return fail(sv->fatal, "server failed: %s", sv->fatal_msg.c_str());
+        sv->pending.push_back(r);
+    }
+    sv->cv.notify_one();
+    return AM_OK;
+}
+
+int am_server_poll(am_server *sv, am_result *out, int32_t max_out, int32_t *n_out)
+{
+    if (!sv || !out || !n_out || max_out < 0) return fail(AM_EINVAL, "bad arguments to am_server_poll");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const int32_t n = (int32_t)std::min<size_t>(sv->done.size(), (size_t)max_out);
+    for (int32_t i = 0; i < n; ++i) out[i] = sv->done[i];
+    sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+    *n_out = n;
+    if (sv->fatal != AM_OK && n == 0) return fail(sv->fatal, "server failed: %s", sv->fatal_msg.c_str());
+    return AM_OK;
+}
+
+double am_server_now(void) { return now_s(); }
+
+int am_server_stats(am_server *sv, double out[4])
+{
+    if (!sv || !out) return fail(AM_EINVAL, "bad arguments to am_server_stats");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    out[0] = (double)sv->n_batches;
+    out[1] = (double)sv->n_requests;
+    out[2] = sv->busy_path_steps;
+    out[3] = (double)sv->alloc.used;
+    return AM_OK;
+}
+
+int am_server_destroy(am_server *sv)
+{
+    if (!sv) return AM_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_one();
+    if (sv->th.joinable()) sv->th.join();
+    int rc = sv->fatal;
+    for (auto &sl : sv->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.staging) (void)hipHostFree(sl.staging);
+        if (sl.h_res) (void)hipHostFree(sl.h_res);
+    }
+    if (sv->pool) (void)hipFree(sv->pool);
+    delete sv;
+    return rc;
+}
+
+
 
 int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left, int32_t *right,
                       double *wl, double *wr, double *sd)

@@ -126,7 +126,7 @@ hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
                                  hipStream_t s);
 hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
-                              int grid, int fp64, int ppt, int degree, hipStream_t s);
+                              int grid, int fp64, int ppt, int degree, bool cooperative, hipStream_t s);
 int sweep_batch_blocks_per_cu(int fp64, int ppt, int degree);
 
 }  // namespace amq

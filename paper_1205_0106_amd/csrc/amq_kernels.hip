@@ -1067,7 +1067,7 @@ hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int
 }
 
 hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
-                              int grid, int fp64, int ppt, int degree, hipStream_t s)
+                              int grid, int fp64, int ppt, int degree, bool cooperative, hipStream_t s)
 {
     const void *f = sweep_batch_lookup(fp64, ppt, degree);
     if (!f) return hipErrorInvalidValue;
@@ -1075,7 +1075,10 @@ hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, con
     const int32_t *to = tile_opt;
     BatchGlobal gg = g;
     void *params[] = {(void *)&o, (void *)&to, (void *)&gg};
-    return hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(kWG), params, 0, s);
+    if (cooperative) return hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(kWG), params, 0, s);
+    // grid sized by the caller so that every in-flight persistent grid is
+    // resident together; the bounded waits end the kernel otherwise
+    return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kWG), params, 0, s);
 }
 
 // ---------------------------------------------------------------------------
