@@ -89,11 +89,14 @@ size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int3
  *   [0] S: paths, [n_dates][ld] of double (AM_FP64) or float (AM_FP32_BULK),
  *       row k-1 holds t_k, column i holds path i;
  *   [1] PV: [ld] per-path cashflow discounted to t0, same type as S;
- *   [2] per-date records: [n_dates+1][32] double; row k (1 <= k < n_dates)
+ *   [2] per-date records: [n_dates+1][40] double; row k (1 <= k < n_dates)
  *       holds the date's regression: [0..7] coefficients of the fitted value
  *       (cashflow discounted to t0) in the engine's standardised basis, [8] 1
  *       if solved / 0 if the date allowed no exercise, [9] in-the-money count,
- *       [10..] the moment sums it was solved from;
+ *       [10..30] the moment sums it was solved from, [32..37] device clock
+ *       stamps (100 MHz) of the date's phases: last arrival seen, partials
+ *       summed, solved, group 0 arrived, group 0 released, group 0 started
+ *       its reduction;
  *   [3] result: [8] double {price, std_err, mean_pv, t0_exercise, n_skipped,
  *       error_flag, 0, 0};
  *   [4] ld (elements, not bytes); [5] total bytes.
@@ -210,6 +213,27 @@ int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left,
  * disabling also clears it. */
 int am_profile_enable(int32_t on);
 int am_profile_read(double ms[2], int64_t *calls);
+
+/* Time the batch with each candidate tile shape (paths per thread: FP32 4
+ * and 16, FP64 2 and 8; two timed runs each after a warm-up), remember the
+ * faster one for this shape class (precision, degree, batch size and total
+ * path-steps rounded to powers of two) for later am_price_batch calls in the
+ * process, and return it in *best_ppt (ms_out: mean milliseconds per
+ * candidate, may be NULL).  Synchronous on hip_stream. */
+int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                      void *d_workspace, size_t ws_bytes, void *hip_stream, int32_t *best_ppt,
+                      double ms_out[2]);
+
+/* A batch captured once as a HIP graph (table uploads from pinned staging,
+ * both kernels, result download) and replayed with one launch.  The
+ * options, workspace and tile choice are fixed at capture. */
+typedef struct am_batch_graph am_batch_graph;
+int am_batch_graph_create(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                          void *d_workspace, size_t ws_bytes, am_batch_graph **out);
+int am_batch_graph_launch(am_batch_graph *graph, void *hip_stream);
+/* Wait for the last launch and write price, std_err per option (2*n doubles). */
+int am_batch_graph_results(am_batch_graph *graph, double *h_out);
+int am_batch_graph_destroy(am_batch_graph *graph);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of pricing requests under an HBM budget.    */

@@ -23,6 +23,7 @@ AM_OK, AM_EINVAL, AM_ENOMEM, AM_EDEVICE, AM_EDIM, AM_EWORKSPACE, AM_ETIMEOUT = 0
 AM_BASIS_MONOMIAL, AM_BASIS_LAGUERRE = 0, 1
 AM_FP64, AM_FP32_BULK = 0, 1
 AM_MAX_DEGREE = 6
+REC = 40            # doubles per per-date record in the workspace
 
 _BASIS_NAMES = {"monomial": AM_BASIS_MONOMIAL, "laguerre": AM_BASIS_LAGUERRE}
 _DTYPE_NAMES = {"fp64": AM_FP64, "f64": AM_FP64, "fp32": AM_FP32_BULK, "fp32_bulk": AM_FP32_BULK,
@@ -127,6 +128,18 @@ def lib():
         L.am_server_stats.restype = ctypes.c_int
         L.am_server_destroy.argtypes = [ctypes.c_void_p]
         L.am_server_destroy.restype = ctypes.c_int
+        L.am_batch_autotune.argtypes = [P(am_option), i32, am_basis, i32, ctypes.c_void_p, sz,
+                                        ctypes.c_void_p, P(i32), P(dbl)]
+        L.am_batch_autotune.restype = ctypes.c_int
+        L.am_batch_graph_create.argtypes = [P(am_option), i32, am_basis, i32, ctypes.c_void_p, sz,
+                                            P(ctypes.c_void_p)]
+        L.am_batch_graph_create.restype = ctypes.c_int
+        L.am_batch_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.am_batch_graph_launch.restype = ctypes.c_int
+        L.am_batch_graph_results.argtypes = [ctypes.c_void_p, P(dbl)]
+        L.am_batch_graph_results.restype = ctypes.c_int
+        L.am_batch_graph_destroy.argtypes = [ctypes.c_void_p]
+        L.am_batch_graph_destroy.restype = ctypes.c_int
         L.am_debug_set_batch_ppt.argtypes = [i32]
         L.am_debug_set_batch_ppt.restype = None
         L.am_last_error.argtypes = []
@@ -273,6 +286,46 @@ def am_price_batch(opts, basis: am_basis, dtype, workspace, stream=None, wait: b
     if wait:
         return np.frombuffer(out, dtype=np.float64).reshape(n, 2).copy()
     return None
+
+
+def am_batch_autotune(opts, basis: am_basis, dtype, workspace, stream=None):
+    """Returns (best paths-per-thread, [ms per candidate])."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    best = ctypes.c_int32()
+    ms = (ctypes.c_double * 2)()
+    _check(lib().am_batch_autotune(opts, len(opts), basis, _dtype(dtype),
+                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best), ms))
+    return best.value, [ms[0], ms[1]]
+
+
+class BatchGraph:
+    """A batch captured as a HIP graph; launch() replays it, results() waits."""
+
+    def __init__(self, opts, basis: am_basis, dtype, workspace):
+        self._opts = opts
+        self._ws = workspace
+        self._h = ctypes.c_void_p()
+        _check(lib().am_batch_graph_create(opts, len(opts), basis, _dtype(dtype),
+                                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                           ctypes.byref(self._h)))
+
+    def launch(self, stream) -> None:
+        _check(lib().am_batch_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def results(self):
+        import numpy as np
+        n = len(self._opts)
+        out = (ctypes.c_double * (2 * n))()
+        _check(lib().am_batch_graph_results(self._h, out))
+        return np.frombuffer(out, dtype=np.float64).reshape(n, 2).copy()
+
+    def close(self) -> None:
+        if self._h:
+            lib().am_batch_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
 
 class Server:
@@ -429,7 +482,7 @@ class Pricer:
         sz = 8 if el == torch.float64 else 4
         S = ws[lay.off_S: lay.off_S + n_dates * lay.ld * sz].view(el).view(n_dates, lay.ld)
         PV = ws[lay.off_PV: lay.off_PV + lay.ld * sz].view(el)
-        rec = ws[lay.off_rec: lay.off_rec + (n_dates + 1) * 32 * 8].view(torch.float64).view(n_dates + 1, 32)
+        rec = ws[lay.off_rec: lay.off_rec + (n_dates + 1) * REC * 8].view(torch.float64).view(n_dates + 1, REC)
         res = ws[lay.off_result: lay.off_result + 64].view(torch.float64)
         return dict(S=S[:, :n_paths], PV=PV[:n_paths], rec=rec, result=res, layout=lay)
 

@@ -1,8 +1,8 @@
 """Build libamqmc.so (HIP, gfx950) in-tree.
 
 Steps: write the Sobol direction-number table (from SciPy's engine, checked
-against its points), embed it with an assembler ``.incbin``, compile the two
-HIP translation units for gfx950 and link the shared library next to this
+against its points), embed it with an assembler ``.incbin``, compile the HIP
+translation units for gfx950 and link the shared library next to this
 file.  Object files go to ``<repo>/_build``.
 """
 from __future__ import annotations
@@ -27,7 +27,8 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["amq_kernels.hip", "amq_engine.hip"]
+SOURCES = ["amq_kernels.hip", "amq_engine.hip", "amq_sweep_f32_mono.hip", "amq_sweep_f32_lag.hip",
+           "amq_sweep_f64_mono.hip", "amq_sweep_f64_lag.hip"]
 
 
 def _table_object() -> str:

@@ -57,7 +57,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     int64_t ld;
     size_t s_bytes;  // element size
-    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, off_shift, off_rep, total;
+    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, off_tpart, off_shift, off_rep, total;
 };
 
 Layout make_layout(int64_t N, int32_t M, int32_t dtype)
@@ -71,7 +71,8 @@ Layout make_layout(int64_t N, int32_t M, int32_t dtype)
     L.off_part = o;   o = align256(o + (size_t)amq::kMaxGroups * amq::kPartStride * 8);
     L.off_rec = o;    o = align256(o + (size_t)(M + 1) * amq::kRec * 8);
     L.off_datec = o;  o = align256(o + (size_t)(M + 1) * sizeof(amq::DateConst));
-    L.off_result = o; o = align256(o + 8 * 8 + 16 * 4);   // result[8] then sync[16]
+    L.off_result = o; o = align256(o + 8 * 8 + amq::kSyncWords * 4);   // result[8], barrier block
+    L.off_tpart = o;  o = align256(o + (size_t)amq::kMaxTeams * amq::kPartStride * 8);
     L.off_shift = o;  o = align256(o + (size_t)amq::kMaxReps * M * 4);
     L.off_rep = o;    o = align256(o + (size_t)amq::kMaxReps * 8);
     L.total = o;
@@ -200,13 +201,13 @@ int get_schedule(DevState *st, int M, const amq::BridgeNode **out)
     return AM_OK;
 }
 
-int groups_per_cu(DevState *st, int fp64, int ppt, int degree)
+int groups_per_cu(DevState *st, int fp64, int laguerre, int ppt, int degree)
 {
-    const long key = ((long)fp64 << 20) | ((long)ppt << 4) | degree;
+    const long key = ((long)laguerre << 24) | ((long)fp64 << 20) | ((long)ppt << 4) | degree;
     std::lock_guard<std::mutex> lk(st->mu);
     auto it = st->occ.find(key);
     if (it != st->occ.end()) return it->second;
-    const int nb = amq::sweep_blocks_per_cu(fp64, ppt, degree);
+    const int nb = amq::sweep_blocks_per_cu(fp64, laguerre, ppt, degree);
     st->occ[key] = nb;
     return nb;
 }
@@ -214,13 +215,13 @@ int groups_per_cu(DevState *st, int fp64, int ppt, int degree)
 const int kPPT32[] = {4, 16, 64, 128};
 const int kPPT64[] = {2, 8, 32, 64};
 
-int choose_plan(DevState *st, int64_t N, int fp64, int degree, Plan *p)
+int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Plan *p)
 {
     const int *ppts = fp64 ? kPPT64 : kPPT32;
     const int n = 4;
     for (int i = 0; i < n; ++i) {
         const int ppt = ppts[i];
-        const int per_cu = groups_per_cu(st, fp64, ppt, degree);
+        const int per_cu = groups_per_cu(st, fp64, laguerre, ppt, degree);
         if (per_cu <= 0) continue;
         int64_t gmax = (int64_t)per_cu * st->num_cu;
         if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
@@ -280,7 +281,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
 {
     const int fp64 = dtype == AM_FP64;
     Plan plan;
-    int rc = choose_plan(st, N, fp64, b.degree, &plan);
+    int rc = choose_plan(st, N, fp64, b.kind == AM_BASIS_LAGUERRE, b.degree, &plan);
     if (rc) return rc;
     const amq::BridgeNode *sched = nullptr;
     rc = get_schedule(st, M, &sched);
@@ -300,6 +301,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
     ga.R = (int32_t)(R < 1 ? 1 : R);
     ga.what = 0;
+    ga.is_call = p->is_call;
     ga.S0 = p->S0; ga.K = p->K; ga.r = p->r; ga.sigma = p->sigma; ga.T = p->T;
     const double dt = p->T / (double)M;
     ga.mu = (p->r - 0.5 * p->sigma * p->sigma) * dt;
@@ -322,6 +324,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     sa.rec = (double *)(ws + L.off_rec);
     sa.result = (double *)(ws + L.off_result);
     sa.sync = (uint32_t *)(ws + L.off_result + 64);
+    sa.tpart = (double *)(ws + L.off_tpart);
     sa.err = sa.sync + 2;
     sa.datec = (const amq::DateConst *)(ws + L.off_datec);
     sa.N = N; sa.ld = L.ld;
@@ -383,8 +386,8 @@ int64_t am_max_paths(int32_t dtype)
     int64_t best = 0;
     for (int i = 0; i < n; ++i) {
         int64_t worst = -1;
-        for (int d = 0; d <= AM_MAX_DEGREE; ++d) {
-            int64_t g = (int64_t)groups_per_cu(st, fp64, ppts[i], d) * st->num_cu;
+        for (int d = 0; d < 2 * (AM_MAX_DEGREE + 1); ++d) {
+            int64_t g = (int64_t)groups_per_cu(st, fp64, d & 1, ppts[i], d >> 1) * st->num_cu;
             if (g > amq::kMaxGroups) g = amq::kMaxGroups;
             const int64_t cap = g * amq::kWG * ppts[i];
             worst = worst < 0 || cap < worst ? cap : worst;
@@ -497,7 +500,7 @@ struct BatchPlan {
     std::vector<int64_t> ld, offS, offPV;
     std::vector<size_t> offDatec, offRec;
     std::vector<int32_t> G, tile_base;
-    size_t off_part = 0, off_res = 0, off_sync = 0, off_gsync = 0, off_desc = 0, off_tiles = 0,
+    size_t off_part = 0, off_res = 0, off_sync = 0, off_tpart = 0, off_gsync = 0, off_desc = 0, off_tiles = 0,
            off_units = 0, total = 0;
     int total_tiles = 0, max_M = 0;
     int64_t total_blocks = 0, max_units = 0;
@@ -536,7 +539,8 @@ int batch_plan(const am_option *opts, int32_t n, int32_t dtype, BatchPlan &P)
         P.offRec[i] = o;   o = align256(o + (size_t)(opts[i].n_dates + 1) * amq::kRec * 8);
     }
     P.off_res = o;   o = align256(o + (size_t)n * 8 * 8);
-    P.off_sync = o;  o = align256(o + (size_t)n * 16 * 4);
+    P.off_sync = o;  o = align256(o + (size_t)n * amq::kSyncWords * 4);
+    P.off_tpart = o; o = align256(o + (size_t)n * amq::kMaxTeams * amq::kPartStride * 8);
     P.off_gsync = o; o = align256(o + 16 * 4);
     P.off_desc = o;  o = align256(o + (size_t)n * sizeof(amq::BatchOpt));
     // tiles: the smallest batch tile (256 paths) bounds the count from above
@@ -548,6 +552,29 @@ int batch_plan(const am_option *opts, int32_t n, int32_t dtype, BatchPlan &P)
     P.total = o;
     (void)tiles;
     return AM_OK;
+}
+
+// Batch tile autotuning: the best paths-per-thread found by am_batch_autotune
+// for a shape class (precision, degree, batch size and total work, both
+// rounded to powers of two), used when no explicit choice is set.
+std::mutex g_tune_mu;
+std::map<long long, int> g_tuned;
+
+long long tune_key(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
+{
+    double work = 0.0;
+    for (int i = 0; i < n; ++i) work += (double)opts[i].n_paths * opts[i].n_dates;
+    const int lw = (int)floor(log2(work > 1.0 ? work : 1.0));
+    const int ln = (int)floor(log2((double)n));
+    return ((long long)dtype << 40) | ((long long)basis.degree << 32) | ((long long)ln << 16) | lw;
+}
+
+int tuned_ppt(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(opts, n, basis, dtype));
+    if (it != g_tuned.end()) return it->second;
+    return dtype == AM_FP64 ? 8 : 16;
 }
 
 int validate_batch(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
@@ -592,6 +619,7 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
     int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
     ga.R = (int32_t)(R < 1 ? 1 : R);
     ga.what = 0;
+    ga.is_call = params->is_call;
     ga.S0 = params->S0; ga.K = params->K; ga.r = params->r; ga.sigma = params->sigma;
     ga.T = dt * (double)n_points;                       // horizon t_m = m dt
     ga.mu = (params->r - 0.5 * params->sigma * params->sigma) * dt;
@@ -632,10 +660,10 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
 {
     int rc = AM_OK;
     const int fp64 = dtype == AM_FP64;
-    const int ppt = g_batch_ppt ? g_batch_ppt : (fp64 ? 8 : 16);
+    const int ppt = g_batch_ppt ? g_batch_ppt : tuned_ppt(opts, n_opts, basis, dtype);
     const int64_t tile = (int64_t)amq::kWG * ppt;
     if (kBatchTileAlign % tile != 0) return fail(AM_EINVAL, "batch tile %lld does not divide the row padding", (long long)tile);
-    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, ppt, basis.degree);
+    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, basis.kind == AM_BASIS_LAGUERRE, ppt, basis.degree);
     if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel for ppt %d degree %d", ppt, basis.degree);
     int capacity = per_cu * st->num_cu;
     if (grid_cap > 0 && grid_cap < capacity) capacity = grid_cap;
@@ -658,7 +686,8 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
         d.datec = (amq::DateConst *)(ws + P.offDatec[i]);
         d.rec = (double *)(ws + P.offRec[i]);
         d.result = (double *)(ws + P.off_res) + (size_t)i * 8;
-        d.sync = (uint32_t *)(ws + P.off_sync) + (size_t)i * 16;
+        d.sync = (uint32_t *)(ws + P.off_sync) + (size_t)i * amq::kSyncWords;
+        d.tpart = (double *)(ws + P.off_tpart) + (size_t)i * amq::kMaxTeams * amq::kPartStride;
         d.N = op.n_paths;
         d.ld = P.ld[i];
         d.M = op.n_dates;
@@ -771,6 +800,155 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
 }
 
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
+
+int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                      void *d_workspace, size_t ws_bytes, void *hip_stream, int32_t *best_ppt,
+                      double ms_out[2])
+{
+    int rc = validate_batch(opts, n_opts, basis, dtype);
+    if (rc) return rc;
+    BatchPlan P;
+    batch_plan(opts, n_opts, dtype, P);
+    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const int cands[2] = {dtype == AM_FP64 ? 2 : 4, dtype == AM_FP64 ? 8 : 16};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int32_t saved = g_batch_ppt;
+    double best = 1e300;
+    int best_c = cands[1];
+    for (int c = 0; c < 2; ++c) {
+        g_batch_ppt = cands[c];
+        double ms = 0.0;
+        for (int rep = 0; rep < 3 && rc == AM_OK; ++rep) {    // first run warms up
+            if (hipEventRecord(e0, stream) != hipSuccess) rc = AM_EDEVICE;
+            if (!rc) rc = enqueue_batch(st, opts, n_opts, basis, dtype, (char *)d_workspace, P, stream, 0,
+                                        true, nullptr, 0);
+            if (!rc && hipEventRecord(e1, stream) != hipSuccess) rc = AM_EDEVICE;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = AM_EDEVICE;
+            float t = 0.f;
+            if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = AM_EDEVICE;
+            if (rep > 0) ms += t;
+        }
+        if (rc) break;
+        ms /= 2.0;
+        if (ms_out) ms_out[c] = ms;
+        if (ms < best) { best = ms; best_c = cands[c]; }
+    }
+    g_batch_ppt = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc == AM_EDEVICE ? fail(AM_EDEVICE, "autotune run failed: %s", g_err.c_str()) : rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(opts, n_opts, basis, dtype)] = best_c;
+    }
+    if (best_ppt) *best_ppt = best_c;
+    return AM_OK;
+}
+
+}  // extern "C"
+
+// A batch captured once as a HIP graph and replayed: table uploads from
+// pinned staging, generation, the persistent sweep (normal launch, grid
+// within the resident capacity) and the result download.
+struct am_batch_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    char *staging = nullptr;
+    double *h_res = nullptr;
+    int32_t n = 0;
+};
+
+extern "C" {
+
+int am_batch_graph_create(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
+                          void *d_workspace, size_t ws_bytes, am_batch_graph **out)
+{
+    if (!out) return fail(AM_EINVAL, "out is NULL");
+    int rc = validate_batch(opts, n_opts, basis, dtype);
+    if (rc) return rc;
+    BatchPlan P;
+    batch_plan(opts, n_opts, dtype, P);
+    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    for (int i = 0; i < n_opts; ++i) {   // schedules are allocated outside the capture
+        const amq::BridgeNode *sc = nullptr;
+        rc = get_schedule(st, opts[i].n_dates, &sc);
+        if (rc) return rc;
+    }
+    std::unique_ptr<am_batch_graph> g(new am_batch_graph);
+    g->n = n_opts;
+    const size_t stage = align256((size_t)n_opts * sizeof(amq::BatchOpt)) + align256((size_t)P.total_blocks * 4) +
+                         (size_t)P.max_units * sizeof(amq::GenUnit) + 4096;
+    if (hipHostMalloc((void **)&g->staging, stage, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_res, (size_t)n_opts * 64 + 64, hipHostMallocDefault) != hipSuccess)
+        return fail(AM_ENOMEM, "pinned buffers for the batch graph failed");
+    HIP_TRY(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    char *ws = (char *)d_workspace;
+    rc = enqueue_batch(st, opts, n_opts, basis, dtype, ws, P, cs, 0, false, g->staging, stage);
+    if (rc == AM_OK) {
+        if (hipMemcpyAsync(g->h_res, ws + P.off_res, (size_t)n_opts * 64, hipMemcpyDeviceToHost, cs) != hipSuccess ||
+            hipMemcpyAsync(g->h_res + (size_t)n_opts * 8, ws + P.off_gsync, 64, hipMemcpyDeviceToHost, cs) != hipSuccess)
+            rc = fail(AM_EDEVICE, "result download could not be captured");
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return fail(AM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    g->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+    *out = g.release();
+    return AM_OK;
+}
+
+int am_batch_graph_launch(am_batch_graph *g, void *hip_stream)
+{
+    if (!g) return fail(AM_EINVAL, "graph is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(hipGraphLaunch(g->exec, s));
+    HIP_TRY(hipEventRecord(g->done, s));
+    return AM_OK;
+}
+
+int am_batch_graph_results(am_batch_graph *g, double *h_out)
+{
+    if (!g || !h_out) return fail(AM_EINVAL, "graph and h_out must be non-NULL");
+    HIP_TRY(hipEventSynchronize(g->done));
+    const uint32_t *gs = (const uint32_t *)(g->h_res + (size_t)g->n * 8);
+    if (gs[1] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
+    for (int i = 0; i < g->n; ++i) {
+        h_out[2 * i] = g->h_res[(size_t)i * 8];
+        h_out[2 * i + 1] = g->h_res[(size_t)i * 8 + 1];
+    }
+    return AM_OK;
+}
+
+int am_batch_graph_destroy(am_batch_graph *g)
+{
+    if (!g) return AM_OK;
+    if (g->done) (void)hipEventSynchronize(g->done);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->done) (void)hipEventDestroy(g->done);
+    if (g->staging) (void)hipHostFree(g->staging);
+    if (g->h_res) (void)hipHostFree(g->h_res);
+    delete g;
+    return AM_OK;
+}
 
 }  // extern "C"
 
@@ -961,7 +1139,7 @@ bool launch_some(am_server *sv, Slot &sl, std::deque<Request> &pend, std::vector
 
 void server_loop(am_server *sv)
 {
-    hipSetDevice(sv->st->dev);
+    (void)hipSetDevice(sv->st->dev);   // the device was validated at create
     std::deque<Request> local;
     std::vector<am_result> out;
     for (;;) {
@@ -1018,7 +1196,7 @@ int am_server_create(const am_server_config *cfg, am_server **out)
     sv->alloc.init(cfg->hbm_budget_bytes);
     const int fp64 = cfg->dtype == AM_FP64;
     const int ppt = fp64 ? 8 : 16;
-    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, ppt, cfg->basis.degree);
+    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, cfg->basis.kind == AM_BASIS_LAGUERRE, ppt, cfg->basis.degree);
     if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel");
     sv->grid_cap = per_cu * st->num_cu / cfg->n_streams;   // in-flight grids fit together
     sv->slots.resize(cfg->n_streams);
@@ -1175,7 +1353,7 @@ int am_debug_generate(int32_t what, const am_params *params, int64_t n_paths, in
     const int64_t ld = (n_paths + 63) / 64 * 64;
     const size_t el = what == 1 ? 4 : (what == 2 ? 8 : (fp64 ? 8 : 4));
     const size_t out_b = (size_t)n_dims * ld * el;
-    const size_t aux_b = align256((size_t)(n_dims + 1) * sizeof(amq::DateConst)) + 256;
+    const size_t aux_b = align256((size_t)(n_dims + 1) * sizeof(amq::DateConst)) + align256(amq::kSyncWords * 4);
     char *d = nullptr;
     if (hipMalloc((void **)&d, align256(out_b) + aux_b) != hipSuccess)
         return fail(AM_ENOMEM, "hipMalloc for the diagnostic output failed");

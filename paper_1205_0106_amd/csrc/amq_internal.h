@@ -10,10 +10,21 @@ constexpr int kWG = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
 constexpr int kMaxSlots = 16;     // bridge register window (tree depth + 2; depth <= 10 for 640 dates)
 constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS) bound this
-constexpr int kRec = 32;          // doubles per date record
+constexpr int kRec = 40;          // doubles per date record
+constexpr int kRecTime = 32;      // record slots 32..37: device clock stamps of the date's phases
 constexpr int kPartStride = 32;   // doubles per workgroup partial-sum slot
 constexpr int kMaxGroups = 2048;  // partial-sum slots in the workspace
 constexpr int kMaxReps = 64;      // randomised QMC replicates per call
+
+// Barrier block of one sweep (uint32 words, one 64-byte line per counter):
+//   line 0: [0] top-level arrivals, [2] error word, [4] ticket (paper kernel);
+//   lines 1 .. kMaxTeams: team arrival counters;
+//   lines 1+kMaxTeams .. 2*kMaxTeams: team release words (epoch numbers).
+// Groups form at most kMaxTeams teams of team_size(G) consecutive groups.
+constexpr int kMaxTeams = 32;
+constexpr int kSyncLine = 16;
+constexpr int kSyncWords = kSyncLine * (1 + 2 * kMaxTeams);
+__host__ __device__ inline uint32_t team_size(uint32_t G) { return (G + kMaxTeams - 1) / kMaxTeams; }
 constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
 
 // One node of the Brownian bridge, in depth-first construction order.  The
@@ -34,7 +45,8 @@ static_assert(sizeof(BridgeNode) == 64, "bridge node is one scalar cache line");
 
 // Per-date constants written by the generation kernel, read by the sweep.
 //   disc = exp(-r t_k); standardised abscissa xs = S * xa + xb with
-//   xa = 1/(K sd_k), xb = -mean_k/sd_k (mean/sd of S_k/K under the model).
+//   xa = 1/(K sd_k), xb = -mean_k/sd_k (mean/sd of S_k/K in the money under
+//   the model).
 struct DateConst {
     double disc, xa, xb, pad;
 };
@@ -53,6 +65,7 @@ struct GenArgs {
     const uint32_t *shift;    // [M] digital shift (randomised QMC) or nullptr
     double S0, K, r, sigma, T;
     double mu, vol;           // (r - sigma^2/2) dt, sigma sqrt(dt)
+    int32_t is_call, pad2;    // payoff side (standardisation of the in-the-money region)
 };
 
 struct SweepArgs {
@@ -61,7 +74,8 @@ struct SweepArgs {
     double *part;             // [kMaxGroups][kPartStride]
     double *rec;              // [M+1][kRec]
     double *result;           // [8]
-    uint32_t *sync;           // [0] arrivals, [1] released epoch
+    uint32_t *sync;           // barrier block [kSyncWords]
+    double *tpart;            // [kMaxTeams][kPartStride] team partial sums
     uint32_t *err;            // error word: a wait ran out (every group exits)
     const DateConst *datec;   // [M+1]
     int64_t N, ld;
@@ -93,7 +107,8 @@ struct alignas(64) BatchOpt {
     DateConst *datec;         // [M+1]
     double *rec;              // [M+1][kRec]
     double *result;           // [8]
-    uint32_t *sync;           // [16] barrier words of this option
+    uint32_t *sync;           // barrier block [kSyncWords] of this option
+    double *tpart;            // [kMaxTeams][kPartStride] team partial sums
     int64_t N, ld;
     int32_t M, G;             // dates, tiles
     int32_t tile_base;        // first partial slot / global tile index
@@ -116,10 +131,11 @@ struct BatchGlobal {
 
 // Launchers (defined with the kernels).
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s);
-// Returns hipErrorInvalidValue if no kernel exists for (fp64, ppt, degree).
+// Returns hipErrorInvalidValue if no kernel exists for (fp64, a.laguerre,
+// ppt, a.degree).
 hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s);
-// Workgroups of the sweep kernel that fit on one CU for (fp64, ppt, degree).
-int sweep_blocks_per_cu(int fp64, int ppt, int degree);
+// Workgroups of the sweep kernel that fit on one CU (0: no such kernel).
+int sweep_blocks_per_cu(int fp64, int laguerre, int ppt, int degree);
 size_t generate_lds_bytes(int M);
 hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
@@ -127,6 +143,12 @@ hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int
                                  hipStream_t s);
 hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
                               int grid, int fp64, int ppt, int degree, bool cooperative, hipStream_t s);
-int sweep_batch_blocks_per_cu(int fp64, int ppt, int degree);
+int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree);
+// Sweep kernel tables, one translation unit per (precision, basis kind);
+// batch != 0 selects the many-option kernel.  Null where not built.
+const void *sweep_table_f32_mono(int ppt, int degree, int batch);
+const void *sweep_table_f32_lag(int ppt, int degree, int batch);
+const void *sweep_table_f64_mono(int ppt, int degree, int batch);
+const void *sweep_table_f64_lag(int ppt, int degree, int batch);
 
 }  // namespace amq

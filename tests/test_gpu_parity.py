@@ -236,7 +236,7 @@ def test_european_mode(amq, orc, pricer, dtype):
 
 def test_t0_exercise_wins(amq, orc, pricer):
     kw = dict(S0=40.0, K=100.0, r=0.08, sigma=0.1, T=1.0)
-    price, se, v = gpu_price(amq, pricer, None, N=4096, M=10, **kw)
+    price, se, v = gpu_price(amq, pricer, None, N=4096, M=10, basis=("monomial", 2), **kw)
     ores, _ = oracle_price(orc, None, N=4096, M=10, basis=("monomial", 2), **kw)
     assert ores.t0_exercise and price == 60.0 and se == 0.0
     assert v["result"].cpu().numpy()[3] == 1.0
@@ -318,7 +318,8 @@ def test_paper_estimator_matches_oracle(amq, orc, pricer, dtype, m, N, call):
     want = orc.paper_estimator(**kw, N=N, m=m, is_call=call)
     log(f"    gpu {price:.10f} oracle {want.price:.10f}")
     assert abs(price - want.price) <= TOL[dtype]
-    assert price >= orc.bs_price(**kw, is_call=call) - TOL[dtype]
+    if N >= 1 << 16:   # perfect foresight exceeds the European value (in expectation)
+        assert price >= orc.bs_price(**kw, is_call=call) - TOL[dtype]
 
 
 # --------------------------------------------------------------------------
