@@ -57,7 +57,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     int64_t ld;
     size_t s_bytes;  // element size
-    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, off_tpart, off_shift, off_rep, total;
+    size_t off_S, off_PV, off_part, off_rec, off_datec, off_result, off_shift, off_rep, total;
 };
 
 Layout make_layout(int64_t N, int32_t M, int32_t dtype)
@@ -68,11 +68,11 @@ Layout make_layout(int64_t N, int32_t M, int32_t dtype)
     size_t o = 0;
     L.off_S = o;      o = align256(o + (size_t)M * (size_t)L.ld * L.s_bytes);
     L.off_PV = o;     o = align256(o + (size_t)L.ld * L.s_bytes);
-    L.off_part = o;   o = align256(o + (size_t)amq::kMaxGroups * amq::kPartStride * 8);
+    // sweep partial-sum rows [2][G][row words] (also the estimator's partial slots)
+    L.off_part = o;   o = align256(o + (size_t)2 * amq::kMaxGroups * amq::kMaxRowWords * 8);
     L.off_rec = o;    o = align256(o + (size_t)(M + 1) * amq::kRec * 8);
     L.off_datec = o;  o = align256(o + (size_t)(M + 1) * sizeof(amq::DateConst));
     L.off_result = o; o = align256(o + 8 * 8 + amq::kSyncWords * 4);   // result[8], barrier block
-    L.off_tpart = o;  o = align256(o + (size_t)amq::kMaxTeams * amq::kPartStride * 8);
     L.off_shift = o;  o = align256(o + (size_t)amq::kMaxReps * M * 4);
     L.off_rep = o;    o = align256(o + (size_t)amq::kMaxReps * 8);
     L.total = o;
@@ -213,12 +213,19 @@ int groups_per_cu(DevState *st, int fp64, int laguerre, int ppt, int degree)
 }
 
 const int kPPT32[] = {4, 16, 64, 128};
-const int kPPT64[] = {2, 8, 32, 64};
+const int kPPT64[] = {2, 8, 16, 64};
 
+// Tile choice for one sweep.  Every date costs one device-wide sum, whose
+// latency grows with the group count G (every group reads every group's
+// row: measured on gfx950 about 4.5 us + 13 ns per group), plus the per-date
+// work, spread over min(G, CUs) compute units.  Among the tiles whose grid is
+// co-resident, take the one with the least modelled time per date.
 int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Plan *p)
 {
     const int *ppts = fp64 ? kPPT64 : kPPT32;
     const int n = 4;
+    double best = 0.0;
+    bool found = false;
     for (int i = 0; i < n; ++i) {
         const int ppt = ppts[i];
         const int per_cu = groups_per_cu(st, fp64, laguerre, ppt, degree);
@@ -226,8 +233,15 @@ int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Pla
         int64_t gmax = (int64_t)per_cu * st->num_cu;
         if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
         const int64_t G = (N + (int64_t)amq::kWG * ppt - 1) / ((int64_t)amq::kWG * ppt);
-        if (G <= gmax) { p->ppt = ppt; p->G = (int)G; return AM_OK; }
+        if (G > gmax) continue;
+        // per-date work: ~40 lane operations per path (binary64: ~2x) at
+        // 64 lanes x 4 SIMDs x 2.4 GHz per CU, on the CUs the grid covers
+        const double cus = (double)(G < st->num_cu ? G : st->num_cu);
+        const double work_us = (double)N * (fp64 ? 80.0 : 40.0) / (cus * 4.0 * 16.0 * 2.4e3);
+        const double t = 4.5 + 0.013 * (double)G + work_us;
+        if (!found || t < best) { best = t; p->ppt = ppt; p->G = (int)G; found = true; }
     }
+    if (found) return AM_OK;
     return fail(AM_EDIM, "n_paths = %lld exceeds what one resident sweep holds on this device",
                 (long long)N);
 }
@@ -307,6 +321,8 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     ga.mu = (p->r - 0.5 * p->sigma * p->sigma) * dt;
     ga.vol = p->sigma * sqrt(dt);
     ga.shift = rep >= 0 ? (const uint32_t *)(ws + L.off_shift) + (size_t)rep * M : nullptr;
+    ga.rows = (uint64_t *)(ws + L.off_part);
+    ga.rows_n = amq::rows_words(plan.G, b.degree);
     ProfRec *pr = nullptr;
     if (g_prof.on) {
         int prc = prof_slot(&pr);
@@ -320,11 +336,10 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     memset(&sa, 0, sizeof sa);
     sa.S = ws + L.off_S;
     sa.pv_out = ws + L.off_PV;
-    sa.part = (double *)(ws + L.off_part);
+    sa.rows = (uint64_t *)(ws + L.off_part);
     sa.rec = (double *)(ws + L.off_rec);
     sa.result = (double *)(ws + L.off_result);
     sa.sync = (uint32_t *)(ws + L.off_result + 64);
-    sa.tpart = (double *)(ws + L.off_tpart);
     sa.err = sa.sync + 2;
     sa.datec = (const amq::DateConst *)(ws + L.off_datec);
     sa.N = N; sa.ld = L.ld;
@@ -500,7 +515,7 @@ struct BatchPlan {
     std::vector<int64_t> ld, offS, offPV;
     std::vector<size_t> offDatec, offRec;
     std::vector<int32_t> G, tile_base;
-    size_t off_part = 0, off_res = 0, off_sync = 0, off_tpart = 0, off_gsync = 0, off_desc = 0, off_tiles = 0,
+    size_t off_part = 0, off_res = 0, off_sync = 0, off_gsync = 0, off_desc = 0, off_tiles = 0,
            off_units = 0, total = 0;
     int total_tiles = 0, max_M = 0;
     int64_t total_blocks = 0, max_units = 0;
@@ -540,14 +555,13 @@ int batch_plan(const am_option *opts, int32_t n, int32_t dtype, BatchPlan &P)
     }
     P.off_res = o;   o = align256(o + (size_t)n * 8 * 8);
     P.off_sync = o;  o = align256(o + (size_t)n * amq::kSyncWords * 4);
-    P.off_tpart = o; o = align256(o + (size_t)n * amq::kMaxTeams * amq::kPartStride * 8);
     P.off_gsync = o; o = align256(o + 16 * 4);
     P.off_desc = o;  o = align256(o + (size_t)n * sizeof(amq::BatchOpt));
     // tiles: the smallest batch tile (256 paths) bounds the count from above
     int64_t max_tiles = 0;
     for (int i = 0; i < n; ++i) max_tiles += P.ld[i] / 256;
     P.off_tiles = o; o = align256(o + (size_t)max_tiles * 4);
-    P.off_part = o;  o = align256(o + (size_t)max_tiles * amq::kPartStride * 8);
+    P.off_part = o;  o = align256(o + (size_t)max_tiles * 2 * amq::kMaxRowWords * 8);   // partial-sum rows
     P.off_units = o; o = align256(o + (size_t)P.max_units * sizeof(amq::GenUnit));
     P.total = o;
     (void)tiles;
@@ -687,12 +701,13 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
         d.rec = (double *)(ws + P.offRec[i]);
         d.result = (double *)(ws + P.off_res) + (size_t)i * 8;
         d.sync = (uint32_t *)(ws + P.off_sync) + (size_t)i * amq::kSyncWords;
-        d.tpart = (double *)(ws + P.off_tpart) + (size_t)i * amq::kMaxTeams * amq::kPartStride;
         d.N = op.n_paths;
         d.ld = P.ld[i];
         d.M = op.n_dates;
         d.G = (int32_t)((op.n_paths + tile - 1) / tile);
         d.tile_base = tiles;
+        d.rows = (uint64_t *)(ws + P.off_part) + (size_t)tiles * 2 * amq::row_words(basis.degree);
+        d.rows_n = amq::rows_words(d.G, basis.degree);
         d.is_call = op.params.is_call;
         d.allow_exercise = op.params.allow_exercise;
         d.S0 = op.params.S0; d.K = op.params.K; d.r = op.params.r; d.sigma = op.params.sigma;
@@ -749,7 +764,6 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     if (pr) HIP_TRY(hipEventRecord(pr->e[1], stream));
     amq::BatchGlobal g;
     memset(&g, 0, sizeof g);
-    g.part = (double *)(ws + P.off_part);
     g.claim = gsync;
     g.err = gsync + 1;
     g.total_tiles = tiles;

@@ -12,19 +12,27 @@ constexpr int kMaxSlots = 16;     // bridge register window (tree depth + 2; dep
 constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS) bound this
 constexpr int kRec = 40;          // doubles per date record
 constexpr int kRecTime = 32;      // record slots 32..37: device clock stamps of the date's phases
-constexpr int kPartStride = 32;   // doubles per workgroup partial-sum slot
-constexpr int kMaxGroups = 2048;  // partial-sum slots in the workspace
+constexpr int kPartStride = 32;   // doubles per workgroup partial slot (estimator kernel)
+constexpr int kMaxGroups = 2048;  // workgroups of one sweep or estimator launch, at most
 constexpr int kMaxReps = 64;      // randomised QMC replicates per call
 
 // Barrier block of one sweep (uint32 words, one 64-byte line per counter):
-//   line 0: [0] top-level arrivals, [2] error word, [4] ticket (paper kernel);
-//   lines 1 .. kMaxTeams: team arrival counters;
-//   lines 1+kMaxTeams .. 2*kMaxTeams: team release words (epoch numbers).
+//   line 0: [2] error word (a wait ran out: every workgroup exits),
+//           [4] ticket (paper kernel);
+//   lines 1 .. kMaxTeams: team arrival counters (monotone; team t has
+//   received all arrivals of epoch e at e * (its member count)).
 // Groups form at most kMaxTeams teams of team_size(G) consecutive groups.
 constexpr int kMaxTeams = 32;
 constexpr int kSyncLine = 16;
-constexpr int kSyncWords = kSyncLine * (1 + 2 * kMaxTeams);
+constexpr int kSyncWords = kSyncLine * (1 + kMaxTeams);
 __host__ __device__ inline uint32_t team_size(uint32_t G) { return (G + kMaxTeams - 1) / kMaxTeams; }
+
+// Partial-sum rows of one sweep: [2 epoch parities][G][row_words] 8-byte
+// words; each word holds an FP64 partial whose two lowest mantissa bits carry
+// epoch & 3 (see allreduce in amq_sync.h).  Zeroed by the generation kernel.
+__host__ __device__ constexpr int row_words(int degree) { return 3 * degree + 3 <= 16 ? 16 : 32; }
+constexpr int kMaxRowWords = 32;
+__host__ __device__ inline int64_t rows_words(int64_t G, int degree) { return 2 * G * row_words(degree); }
 constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
 
 // One node of the Brownian bridge, in depth-first construction order.  The
@@ -66,16 +74,17 @@ struct GenArgs {
     double S0, K, r, sigma, T;
     double mu, vol;           // (r - sigma^2/2) dt, sigma sqrt(dt)
     int32_t is_call, pad2;    // payoff side (standardisation of the in-the-money region)
+    uint64_t *rows;           // partial-sum rows to zero (with the barrier words)
+    int64_t rows_n;           // their count in 8-byte words
 };
 
 struct SweepArgs {
     const void *S;            // [M][ld] T
     void *pv_out;             // [ld] T
-    double *part;             // [kMaxGroups][kPartStride]
+    uint64_t *rows;           // partial-sum rows [2][G][row_words(degree)]
     double *rec;              // [M+1][kRec]
     double *result;           // [8]
     uint32_t *sync;           // barrier block [kSyncWords]
-    double *tpart;            // [kMaxTeams][kPartStride] team partial sums
     uint32_t *err;            // error word: a wait ran out (every group exits)
     const DateConst *datec;   // [M+1]
     int64_t N, ld;
@@ -108,7 +117,8 @@ struct alignas(64) BatchOpt {
     double *rec;              // [M+1][kRec]
     double *result;           // [8]
     uint32_t *sync;           // barrier block [kSyncWords] of this option
-    double *tpart;            // [kMaxTeams][kPartStride] team partial sums
+    uint64_t *rows;           // partial-sum rows [2][G][row_words(degree)] of this option
+    int64_t rows_n;           // their count in 8-byte words (zeroed by generation)
     int64_t N, ld;
     int32_t M, G;             // dates, tiles
     int32_t tile_base;        // first partial slot / global tile index
@@ -122,7 +132,6 @@ struct GenUnit {              // one generation workgroup: blocks [b0, b1) of op
 };
 
 struct BatchGlobal {
-    double *part;             // [total tiles][kPartStride]
     uint32_t *claim;          // tile claim counter (zeroed by generation)
     uint32_t *err;            // error word (zeroed by generation)
     int32_t total_tiles, laguerre;

@@ -8,6 +8,7 @@
 // precision and basis kind in amq_sweep_*.hip); this file dispatches to them.
 //
 // Compiled for gfx950 only.
+#include "amq_math.h"
 #include "amq_sync.h"
 
 #include <math.h>
@@ -256,21 +257,30 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     const int offL = gl & 7, offH = 8 + (gl >> 3);
     const int xsel = lane == 63 ? 1 : 0;
 
-    const T S0 = (T)a.S0;
-    // binary32 uses exp2: fold log2(e) into the drift and volatility
-    const T mu = sizeof(T) == 4 ? (T)(a.mu * 1.4426950408889634) : (T)a.mu;
-    const T vol = sizeof(T) == 4 ? (T)(a.vol * 1.4426950408889634) : (T)a.vol;
+    // The bridge and the exponent run in binary64 for both storage types;
+    // binary32 storage rounds the binary64 value once (the exercise decisions
+    // downstream are sensitive to path-value errors well below a binary32 ulp,
+    // so nothing but the final rounding is left in binary32).  Only the
+    // inverse normal is evaluated in the storage precision.
+    const double S0 = a.S0, mu = a.mu, vol = a.vol;
+    // Padding paths (past N) hold K rounded in the storage precision away
+    // from the money, so h(S) <= 0 in binary64 and the sweep never counts
+    // them in the money.
+    T Kp = (T)a.K;
+    if constexpr (sizeof(T) == 4) {
+        if (!a.is_call && (double)Kp < a.K) Kp = nextafterf(Kp, INFINITY);
+        if (a.is_call && (double)Kp > a.K) Kp = nextafterf(Kp, -INFINITY);
+    }
 
-    T W[kMaxSlots];
+    double W[kMaxSlots];
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) W[q] = T(0);
+    for (int q = 0; q < kMaxSlots; ++q) W[q] = 0.0;
 
     for (int64_t w = w0; w < w1; ++w) {
         const int64_t i = (w << 6) + lane;
         const bool valid = i < a.N;
         if (WHAT == 0 && (w << 6) >= a.N) {
-            // padding block: S = K on every date (out of the money, see the sweep)
-            const T Kp = (T)a.K;
+            // padding block: out of the money on every date
             for (int m = 0; m < M; ++m) ((T *)a.S)[(size_t)m * a.ld + i] = Kp;
             continue;
         }
@@ -288,18 +298,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = (double)z;
                 continue;
             }
-            T wv;
-            if (sizeof(T) == 4)
-                wv = (T)nd.fwl * W[nd.sl] + (T)nd.fwr * W[nd.sr] + (T)nd.fsd * z;
-            else
-                wv = (T)nd.wl * W[nd.sl] + (T)nd.wr * W[nd.sr] + (T)nd.sd * z;
+            const double wv = nd.wl * W[nd.sl] + nd.wr * W[nd.sr] + nd.sd * (double)z;
             W[nd.dst] = wv;
-            T Sv;
-            if (sizeof(T) == 4)
-                Sv = S0 * __builtin_amdgcn_exp2f(fmaf((float)vol, (float)wv, (float)mu * nd.fm));
-            else
-                Sv = S0 * exp((double)mu * (double)nd.m + (double)vol * (double)wv);
-            ((T *)a.S)[(size_t)(nd.m - 1) * a.ld + i] = valid ? Sv : (T)a.K;
+            const double e = mu * (double)nd.m + vol * wv;
+            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly(e) : exp(e)));
+            ((T *)a.S)[(size_t)(nd.m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {
             const int c = min(__builtin_ctzll((uint64_t)w + 2u) + 6, 31);
@@ -326,6 +329,10 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
     const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const int64_t w0 = gw * a.R;
     const int64_t w1 = min(w0 + (int64_t)a.R, a.nblocks);
+    // the sweep's partial-sum rows start each launch at tag 0
+    if (WHAT == 0)
+        for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < a.rows_n; q += (int64_t)gridDim.x * kWG)
+            a.rows[q] = 0ull;
     gen_body<T, WHAT, MID>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
 }
 
@@ -424,6 +431,8 @@ __device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t
     a.mu = o.mu; a.vol = o.vol;
     a.shift = nullptr;
     a.is_call = o.is_call;
+    a.rows = o.rows;
+    a.rows_n = 0;   // cleared by the option's first unit
     return a;
 }
 
@@ -436,6 +445,8 @@ gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ 
     const BatchOpt o = opts[u.opt];
     if (blockIdx.x == 0 && threadIdx.x < 16) gsync[threadIdx.x] = 0u;
     const GenArgs a = gen_args_of(o, V);
+    if (u.b0 == 0)   // the option's first unit clears its partial-sum rows
+        for (int64_t q = threadIdx.x; q < o.rows_n; q += kWG) o.rows[q] = 0ull;
     const int64_t per = (u.b1 - u.b0 + kWaves - 1) / kWaves;
     const int64_t w0 = u.b0 + (int64_t)(threadIdx.x >> 6) * per;
     const int64_t w1 = min(w0 + per, u.b1);

@@ -1,0 +1,34 @@
+// amq_math.h — binary64 helpers shared by the generation and sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace amq {
+
+// exp(x) in binary64: n = rint(x log2(e)), g = x - n ln 2 (Cody-Waite: ln 2
+// split into a 53-bit head and its tail, each product taken exactly inside
+// an fma), |g| <= 0.3466; exp(x) = 2^n e^g with e^g from its Taylor series to
+// degree 12 (truncation below 0.3466^13 / 13! < 2e-16 relative).  Intended
+// for the arguments the kernels produce (|x| < 700); very negative x
+// underflows to 0 through ldexp.
+__device__ __forceinline__ double exp_poly(double x)
+{
+    const double n = rint(x * 1.4426950408889634);
+    const double g = fma(-n, 2.3190468138462996e-17, fma(-n, 0.69314718055994529, x));
+    double p = 1.0 / 479001600.0;                  // 1/12!
+    p = fma(p, g, 1.0 / 39916800.0);               // 1/11!
+    p = fma(p, g, 1.0 / 3628800.0);
+    p = fma(p, g, 1.0 / 362880.0);
+    p = fma(p, g, 1.0 / 40320.0);
+    p = fma(p, g, 1.0 / 5040.0);
+    p = fma(p, g, 1.0 / 720.0);
+    p = fma(p, g, 1.0 / 120.0);
+    p = fma(p, g, 1.0 / 24.0);
+    p = fma(p, g, 1.0 / 6.0);
+    p = fma(p, g, 0.5);
+    p = fma(p, g, 1.0);
+    p = fma(p, g, 1.0);
+    return ldexp(p, (int)n);
+}
+
+}  // namespace amq

@@ -4,67 +4,61 @@
 // cashflow mean; single-option and many-option (batch) forms (gfx950).
 #pragma once
 
+#include "amq_math.h"
 #include "amq_sync.h"
 
 namespace amq {
 
 // FP64 normal-equation solve for the p = D+1 coefficients from Hankel moments
 // tot[0..2D] (sum of wA xs^q), tot[2D+1 .. 3D+1] (sum of wB xs^a pv) and the
-// in-the-money count tot[3D+2].  Equilibrated Cholesky in LDS (one thread);
-// a date with fewer in-the-money paths than p or a pivot below 1e-14 (on the
-// unit-diagonal matrix) allows no exercise.  rec: [0..7] coefficients in the
-// standardised basis, [8] solved flag, [9] count, [10..] the moments.
+// in-the-money count tot[3D+2].  Equilibrated Cholesky by one thread, with
+// the factor and work vectors in LDS (registers here would be allocated in
+// every lane beside the resident cashflows); a date with fewer in-the-money
+// paths than p or a pivot below 1e-14 (on the unit-diagonal matrix) allows no
+// exercise.  beta: [0..7] coefficients in the standardised basis (zero past
+// p), [8] solved flag, [9] in-the-money count.
 template <int D>
-__device__ void solve_date(const double *tot, double *rec, double (*L)[8], double *w)
+__device__ void solve_date(const double *tot, double *beta, double (*L)[8], double *w)
 {
     constexpr int P = D + 1, NA = 2 * D + 1;
-    const double n = tot[NA + P];
+    const double n = rint(tot[NA + P]);
     bool ok = n >= (double)P;
-    double *sc = w, *y = w + 8, *gam = w + 16;
+    double *sc = w, *rl = w + 8, *y = w + 16, *gam = w + 24;
     for (int i = 0; i < P; ++i) {
         const double d = tot[2 * i];
         ok = ok && (d > 0.0);
         sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
     }
-    for (int j = 0; j < P && ok; ++j) {
+    for (int j = 0; j < P; ++j) {
         double d = tot[2 * j] * sc[j] * sc[j];
         for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
         ok = ok && (d > 1e-14);
-        const double ljj = d > 0.0 ? sqrt(d) : 1.0;
-        L[j][j] = ljj;
+        rl[j] = 1.0 / (d > 1e-14 ? sqrt(d) : 1.0);
         for (int i = j + 1; i < P; ++i) {
             double e = tot[i + j] * sc[i] * sc[j];
             for (int l = 0; l < j; ++l) e -= L[i][l] * L[j][l];
-            L[i][j] = e / ljj;
+            L[i][j] = e * rl[j];
         }
     }
-    if (ok) {
-        for (int i = 0; i < P; ++i) {
-            double e = tot[NA + i] * sc[i];
-            for (int l = 0; l < i; ++l) e -= L[i][l] * y[l];
-            y[i] = e / L[i][i];
-        }
-        for (int i = P - 1; i >= 0; --i) {
-            double e = y[i];
-            for (int l = i + 1; l < P; ++l) e -= L[l][i] * gam[l];
-            gam[i] = e / L[i][i];
-        }
+    for (int i = 0; i < P; ++i) {
+        double e = tot[NA + i] * sc[i];
+        for (int l = 0; l < i; ++l) e -= L[i][l] * y[l];
+        y[i] = e * rl[i];
     }
-    for (int i = 0; i < 8; ++i) rec[i] = (i < P && ok) ? gam[i] * sc[i] : 0.0;
-    rec[8] = ok ? 1.0 : 0.0;
-    rec[9] = n;
-    for (int q = 0; q < NA + P + 1 && q < 22; ++q) rec[10 + q] = tot[q];
+    for (int i = P - 1; i >= 0; --i) {
+        double e = y[i];
+        for (int l = i + 1; l < P; ++l) e -= L[l][i] * gam[l];
+        gam[i] = e * rl[i];
+    }
+    for (int i = 0; i < 8; ++i) beta[i] = (i < P && ok) ? gam[i] * sc[i] : 0.0;
+    beta[8] = ok ? 1.0 : 0.0;
+    beta[9] = n;
 }
 
-template <typename T> __device__ __forceinline__ T lag_weight(T s, T wc);
-// exp(-x/2) with x = S/K: binary32 via exp2 (wc = -log2(e)/(2K)), binary64 exact form
-template <> __device__ __forceinline__ float lag_weight<float>(float s, float wc)
+// Laguerre weight exp(-x/2) with x = S/K (wc = -1/(2K)), binary64.
+__device__ __forceinline__ double lag_weight(double s, double wc)
 {
-    return __builtin_amdgcn_exp2f(s * wc);
-}
-template <> __device__ __forceinline__ double lag_weight<double>(double s, double wc)
-{
-    return exp(s * wc);
+    return exp_poly(s * wc);
 }
 
 // 16-byte vector of path values: 4 binary32 or 2 binary64 consecutive paths.
@@ -93,63 +87,61 @@ struct SweepShape {
     static constexpr int WAVES = KEEP ? 2 : 2;
 };
 
-// Per-thread in-the-money moments over a block of path values.
-template <typename T, int D>
-struct MomBlock {
-    static constexpr int NA = 2 * D + 1, NB = D + 1;
-    T am[NA], ab[NB];
-    __device__ __forceinline__ void clear()
-    {
-#pragma unroll
-        for (int q = 0; q < NA; ++q) am[q] = T(0);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) ab[q] = T(0);
-    }
-    // s: path value, pvj: its cashflow discounted to t0
-    __device__ __forceinline__ int add(T s, T pvj, bool valid, T K, bool call, T xa, T xb,
-                                       bool lag, T wc)
-    {
-        const T h = call ? s - K : K - s;
-        const bool itm = valid && (h > T(0));
-        const T xs = s * xa + xb;
-        T wA = T(1), wB = T(1);
-        if (lag) {
-            const T w = lag_weight<T>(s, wc);
-            wA = w * w;
-            wB = w;
-        }
-        T pa = itm ? wA : T(0);
-        am[0] += pa;
-#pragma unroll
-        for (int q = 1; q < NA; ++q) { pa *= xs; am[q] += pa; }
-        T pb = itm ? wB * pvj : T(0);
-        ab[0] += pb;
-#pragma unroll
-        for (int q = 1; q < NB; ++q) { pb *= xs; ab[q] += pb; }
-        return itm ? 1 : 0;
-    }
-    __device__ __forceinline__ void flush(double *acc) const
-    {
-#pragma unroll
-        for (int q = 0; q < NA; ++q) acc[q] += (double)am[q];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) acc[NA + q] += (double)ab[q];
-    }
-};
+// The per-path arithmetic of the sweep is binary64 for both storage types
+// (path values and cashflows are stored in T): the least-squares fit and the
+// exercise test feed back into every later date, and binary32 arithmetic
+// there moves some prices by more than the binary32 tolerance.  On gfx950
+// without packed binary32 math a binary64 FMA issues at the binary32 rate.
 
-template <typename T, int D>
-__device__ __forceinline__ T exercise_update(T s, T pvj, bool valid, T K, bool call, T xa, T xb,
-                                             T dk, const T *gam, bool lag, T wc)
+// Adds path value s (cashflow pvj discounted to t0) to the in-the-money
+// moments acc[0..NA-1] (sum of wA xs^q) and acc[NA..NA+NB-1] (sum of wB xs^q
+// pvj); returns 1 if the path is in the money.
+template <int D, bool LAG>
+__device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double K, bool call, double xa,
+                                           double xb, double wc)
+{
+    constexpr int NA = 2 * D + 1, NB = D + 1;
+    const double h = call ? s - K : K - s;
+    const bool itm = h > 0.0;
+    const double xs = fma(s, xa, xb);
+    double wA = 1.0, wB = 1.0;
+    if (LAG) {
+        const double w = lag_weight(s, wc);
+        wA = w * w;
+        wB = w;
+    }
+    double pa = itm ? wA : 0.0;
+    acc[0] += pa;
+#pragma unroll
+    for (int q = 1; q < NA; ++q) { pa *= xs; acc[q] += pa; }
+    double pb = itm ? wB * pvj : 0.0;
+    acc[NA] += pb;
+#pragma unroll
+    for (int q = 1; q < NB; ++q) { pb *= xs; acc[NA + q] += pb; }
+    // pin the accumulators here: without this the optimizer sinks the sums
+    // of a whole unrolled run of paths to its end, keeping every path's
+    // powers live at once
+#pragma unroll
+    for (int q = 0; q < NA + NB; ++q) asm volatile("" : "+v"(acc[q]));
+    return itm ? 1 : 0;
+}
+
+// Exercise update at a date: exercise (cashflow dk h) when in the money and
+// dk h exceeds the fitted continuation; else keep pvj.
+template <typename T, int D, bool LAG>
+__device__ __forceinline__ T exercise_update(T s_t, T pvj, double K, bool call, double xa, double xb, double dk,
+                                             const double *gam, double wc)
 {
     constexpr int P = D + 1;
-    const T h = call ? s - K : K - s;
-    const T xs = s * xa + xb;
-    T cont = gam[P - 1];
+    const double s = (double)s_t;
+    const double h = call ? s - K : K - s;
+    const double xs = fma(s, xa, xb);
+    double cont = gam[P - 1];
 #pragma unroll
-    for (int q = P - 2; q >= 0; --q) cont = cont * xs + gam[q];
-    if (lag) cont *= lag_weight<T>(s, wc);
-    const T ex = dk * h;
-    return (valid && (h > T(0)) && (ex > cont)) ? ex : pvj;
+    for (int q = P - 2; q >= 0; --q) cont = fma(cont, xs, gam[q]);
+    if (LAG) cont *= lag_weight(s, wc);
+    const double ex = dk * h;
+    return (h > 0.0 && ex > cont) ? (T)ex : pvj;
 }
 
 // ---------------------------------------------------------------------------
@@ -163,38 +155,36 @@ __device__ __forceinline__ T exercise_update(T s, T pvj, bool valid, T K, bool c
 //   abscissa xs; weights wA = wB = 1 for monomials, wA = w^2, wB = w with
 //   w = exp(-x/2) for Laguerre: same span as the requested basis) of pv, the
 //   cashflow discounted to t0, so the exercise test is disc_k * h > fit;
-//   arrive; the last group sums the partial slots in fixed order, solves and
-//   publishes; the others wait (bounded) and read the coefficients;
-//   exercise update.
-// KEEP: path values held in registers across the barrier, next date
-// prefetched before waiting.  Otherwise the date is streamed twice (moments,
+//   a device-wide fixed-order sum that every group receives (allreduce);
+//   every group solves the same normal equations (bitwise the same
+//   coefficients; group 0 keeps the date record); exercise update.
+// KEEP: path values held in registers across the device-wide sum, next
+// date prefetched before waiting.  Otherwise the date is streamed twice (moments,
 // update) through a ring of PD vector loads in flight per thread.
-// binary32 moments are summed over blocks of 8 paths, then carried in FP64.
-// Rows are padded to a multiple of every tile size with S = K, so padded
-// paths are never in the money and keep pv = 0: no bounds checks.
+// Per-path arithmetic is binary64 for both storage types (see moments_add).
+// Rows are padded to a multiple of every tile size with S = K (rounded away
+// from the money in binary32), so padded paths are never in the money and
+// keep pv = 0: no bounds checks.
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, int D, bool LAG>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                            uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
-                                           double (*s_red)[32], double (*s_red8)[32], double *s_tot,
-                                           double (*s_L)[8], double *s_w, double *s_beta, int *s_flag)
+                                           double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
+                                           double *s_w, int *s_flag)
 {
     using SH = SweepShape<T, PPT>;
     constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
     constexpr bool KEEP = SH::KEEP;
     constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
     constexpr int NV = NA + NB + 1;
-    // binary32 block length (paths); it must divide PPT so every block is flushed
-    constexpr int BLK = sizeof(T) == 4 ? (PPT < 8 ? PPT : 8) : PPT;
-    static_assert(PPT % BLK == 0, "block length must divide the paths per thread");
+    constexpr int RW = row_words(D);
     constexpr uint32_t JS = 64 * VW;                 // element stride between a lane's vectors
 
     const int tid = threadIdx.x;
     const int64_t ld = a.ld;
-    const T K = (T)a.K;
+    const double K = a.K;
     const bool call = a.is_call != 0;
-    constexpr bool lag = LAG;   // Laguerre weights (else monomials)
-    const T wc = sizeof(T) == 4 ? (T)(-1.4426950408889634 / (2.0 * a.K)) : (T)(-0.5 / a.K);
+    const double wc = -0.5 / a.K;   // Laguerre weight exponent per unit S
     const uint32_t G = (uint32_t)a.G;
     const int64_t tile0 = (int64_t)gid * kWG * PPT;
     const uint32_t voff = (e0 - (uint32_t)tile0) * (uint32_t)sizeof(T);   // byte offset in the tile
@@ -210,15 +200,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 
     {
         const T *row = S + (size_t)(a.M - 1) * ld;
-        const T dM = (T)a.datec[a.M].disc;
+        const double dM = a.datec[a.M].disc;
+        // streamed through the same ring as the date passes (issuing every
+        // load at once would hold a second copy of pv[] in registers)
+        Vec<T> ring[PD];
+#pragma unroll
+        for (int q = 0; q < PD; ++q) ring[q] = vload(row, q);
 #pragma unroll
         for (int jj = 0; jj < NVEC; ++jj) {
-            const Vec<T> v = vload(row, jj);
+            const Vec<T> v = ring[jj % PD];
+            if (jj + PD < NVEC) ring[jj % PD] = vload(row, jj + PD);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
-                const T h = call ? v.v[e] - K : K - v.v[e];
-                pv[jj * VW + e] = h > T(0) ? dM * h : T(0);
+                const double sv = (double)v.v[e];
+                const double h = call ? sv - K : K - sv;
+                pv[jj * VW + e] = h > 0.0 ? (T)(dM * h) : T(0);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -232,22 +231,19 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     }
     for (int k = a.M - 1; k >= 1; --k) {
         const DateConst dc = a.datec[k];
-        const T xa = (T)dc.xa, xb = (T)dc.xb, dk = (T)dc.disc;
+        const double xa = dc.xa, xb = dc.xb, dk = dc.disc;
         const T *row = S + (size_t)(k - 1) * ld;
 
         double acc[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         int cnt = 0;
-        MomBlock<T, D> mb;
-        mb.clear();
         if (KEEP) {
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
-                    cnt += mb.add(sc[jj].v[e], pv[jj * VW + e], true, K, call, xa, xb, lag, wc);
-                    if (((jj * VW + e + 1) % BLK) == 0) { mb.flush(acc); mb.clear(); }
+                    cnt += moments_add<D, LAG>(acc, (double)sc[jj].v[e], (double)pv[jj * VW + e], K, call, xa, xb, wc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -262,8 +258,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
-                    cnt += mb.add(cur.v[e], pv[jj * VW + e], true, K, call, xa, xb, lag, wc);
-                    if (((jj * VW + e + 1) % BLK) == 0) { mb.flush(acc); mb.clear(); }
+                    cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], K, call, xa, xb, wc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -274,53 +269,45 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         group_sum<NV>(acc, s_red);
         ++epoch;
         // (a clock read before group_sum would pin the moment pass's schedule)
-        const uint64_t c_arr = __builtin_amdgcn_s_memrealtime();
-        if (tid == 0 && gid == 0) a.rec[(size_t)k * kRec + kRecTime + 5] = (double)c_arr;
-        const bool last = arrive_tree<NV>(acc, gid, G, a.part, a.tpart, a.sync, epoch, s_tot, s_red8, s_flag);
+        const uint64_t c_sum = __builtin_amdgcn_s_memrealtime();
 
         if (KEEP && k >= 2) {
+            // next date's values: in flight while the epoch completes
             const T *nrow = S + (size_t)(k - 2) * ld;
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) sn[jj] = vload(nrow, jj);
         }
-
-        if (last) {
-            if (tid == 0) {
-                const uint64_t c1 = __builtin_amdgcn_s_memrealtime();
-                double *rec = a.rec + (size_t)k * kRec;
-                solve_date<D>(s_tot, rec, s_L, s_w);
-                const uint64_t c2 = __builtin_amdgcn_s_memrealtime();
-                rec[kRecTime + 0] = (double)c_arr;   // top-last group arrived
-                rec[kRecTime + 1] = (double)c1;      // partials summed (both levels)
-                rec[kRecTime + 2] = (double)c2;      // solved
-                release_all(a.sync, G, epoch);
-            }
+        if (!allreduce<NV, RW>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
+            alive = false;
+            return;
         }
-        if (tid == 0 && gid == 0) a.rec[(size_t)k * kRec + kRecTime + 3] = (double)__builtin_amdgcn_s_memrealtime();
         if (tid == 0) {
-            const bool okw = wait_release(release_word(a.sync, G, gid), a.err, epoch, a.spin_limit);
-            if (gid == 0) a.rec[(size_t)k * kRec + kRecTime + 4] = (double)__builtin_amdgcn_s_memrealtime();
-            s_flag[1] = okw ? 1 : 0;
-            if (okw) {
-                const double *rec = a.rec + (size_t)k * kRec;
+            const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
+            solve_date<D>(s_tot, s_beta, s_L, s_w);
+            if (gid == 0) {
+                // every group solved the same system; group 0 keeps the record
+                double *rec = a.rec + (size_t)k * kRec;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) s_beta[q] = rec[q];
+                for (int q = 0; q < 10; ++q) rec[q] = s_beta[q];
+                for (int q = 0; q < NV && q < 22; ++q) rec[10 + q] = s_tot[q];
+                rec[kRecTime + 0] = (double)c_sum;                                // moments summed in the group
+                rec[kRecTime + 1] = (double)c_all;                                // device-wide totals in hand
+                rec[kRecTime + 2] = (double)__builtin_amdgcn_s_memrealtime();     // solved
             }
         }
         __syncthreads();
-        if (!s_flag[1]) { alive = false; return; }
 
         if (s_beta[8] != 0.0) {
-            T gam[P];
+            double gam[P];
 #pragma unroll
-            for (int q = 0; q < P; ++q) gam[q] = (T)s_beta[q];
+            for (int q = 0; q < P; ++q) gam[q] = s_beta[q];
             if (KEEP) {
 #pragma unroll
                 for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
-                        pv[jj * VW + e] = exercise_update<T, D>(sc[jj].v[e], pv[jj * VW + e], true, K,
-                                                                call, xa, xb, dk, gam, lag, wc);
+                        pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], K, call, xa,
+                                                                     xb, dk, gam, wc);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
@@ -335,8 +322,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
-                        pv[jj * VW + e] = exercise_update<T, D>(cur.v[e], pv[jj * VW + e], true, K,
-                                                                call, xa, xb, dk, gam, lag, wc);
+                        pv[jj * VW + e] = exercise_update<T, D, LAG>(cur.v[e], pv[jj * VW + e], K, call, xa, xb,
+                                                                     dk, gam, wc);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     __builtin_amdgcn_sched_barrier(0);
@@ -347,16 +334,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) sc[jj] = sn[jj];
         }
-        __syncthreads();   // s_beta / s_flag reuse
+        __syncthreads();   // s_beta reuse
     }
 }
 
 // Epilogue (eqs. (6)-(8)): FP64 sums of the discounted cashflows and their
-// squares through one more barrier; the last group writes the result.
-template <typename T, int PPT>
+// squares through one more device-wide sum; group 0 writes the result.
+template <typename T, int PPT, int D>
 __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, uint32_t e0,
                                             const T (&pv)[PPT], uint32_t epoch, double (*s_red)[32],
-                                            double (*s_red8)[32], double *s_tot, int *s_flag)
+                                            double *s_tot, int *s_flag)
 {
     constexpr int VW = 16 / sizeof(T), NVEC = PPT / VW;
     constexpr uint32_t JS = 64 * VW;
@@ -379,8 +366,10 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
     group_sum<2>(fin, s_red);
     ++epoch;
     const uint32_t G = (uint32_t)a.G;
-    const bool last = arrive_tree<2>(fin, gid, G, a.part, a.tpart, a.sync, epoch, s_tot, s_red8, s_flag);
-    if (last) {
+    if (!allreduce<2, row_words(D)>(fin, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
+                                    s_flag))
+        return;
+    if (gid == 0) {
         if (tid == 0) {
             const double n = (double)N;
             const double s1 = s_tot[0], s2 = s_tot[1];
@@ -433,21 +422,20 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
 {
     static_assert(PPT % (16 / sizeof(T)) == 0, "PPT must be a multiple of the vector width");
     __shared__ double s_red[kWaves][32];
-    __shared__ double s_red8[8][32];
     __shared__ double s_tot[32];
-    __shared__ double s_L[8][8];
-    __shared__ double s_w[24];
     __shared__ double s_beta[10];
-    __shared__ int s_flag[2];
+    __shared__ double s_L[8][8];
+    __shared__ double s_w[32];
+    __shared__ int s_flag[1 + kWaves];
 
     const uint32_t gid = blockIdx.x;
     const uint32_t e0 = tile_e0<T, PPT>(gid);
     T pv[PPT];
     uint32_t epoch = 0;
     bool alive = true;
-    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, s_red, s_red8, s_tot, s_L, s_w, s_beta, s_flag);
+    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w, s_flag);
     if (!alive) return;
-    sweep_final<T, PPT>(a, gid, e0, pv, epoch, s_red, s_red8, s_tot, s_flag);
+    sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
 }
 
 template <typename T, int PPT, int D, bool LAG>
@@ -456,12 +444,11 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
                    BatchGlobal g)
 {
     __shared__ double s_red[kWaves][32];
-    __shared__ double s_red8[8][32];
     __shared__ double s_tot[32];
-    __shared__ double s_L[8][8];
-    __shared__ double s_w[24];
     __shared__ double s_beta[10];
-    __shared__ int s_flag[2];
+    __shared__ double s_L[8][8];
+    __shared__ double s_w[32];
+    __shared__ int s_flag[1 + kWaves];
     __shared__ int s_claim;
 
     for (;;) {
@@ -478,11 +465,10 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
         SweepArgs a;
         a.S = o.S;
         a.pv_out = o.pv;
-        a.part = g.part + (size_t)o.tile_base * kPartStride;
+        a.rows = o.rows;
         a.rec = o.rec;
         a.result = o.result;
         a.sync = o.sync;
-        a.tpart = o.tpart;
         a.err = g.err;
         a.datec = o.datec;
         a.N = o.N; a.ld = o.ld;
@@ -498,10 +484,10 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
         T pv[PPT];
         uint32_t epoch = 0;
         bool alive = true;
-        sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, s_red, s_red8, s_tot, s_L,
-                              s_w, s_beta, s_flag);
+        sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w,
+                                   s_flag);
         if (!alive) return;
-        sweep_final<T, PPT>(a, gid, e0, pv, epoch, s_red, s_red8, s_tot, s_flag);
+        sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
     }
 }
 
@@ -533,7 +519,7 @@ inline const void *sweep_entry(int degree)
 }
 
 // Paths per thread built: binary32 4, 16, 64, 128 (batch 4, 16); binary64
-// 2, 8, 32, 64 (batch 2, 8).
+// 2, 8, 16, 64 (batch 2, 8).
 template <typename T, bool LAG>
 inline const void *sweep_table(int ppt, int degree, int batch)
 {
@@ -548,7 +534,7 @@ inline const void *sweep_table(int ppt, int degree, int batch)
         switch (ppt) {
         case 2: return sweep_entry<T, 2, LAG, false>(degree);
         case 8: return sweep_entry<T, 8, LAG, false>(degree);
-        case 32: return sweep_entry<T, 32, LAG, false>(degree);
+        case 16: return sweep_entry<T, 16, LAG, false>(degree);
         case 64: return sweep_entry<T, 64, LAG, false>(degree);
         default: return nullptr;
         }

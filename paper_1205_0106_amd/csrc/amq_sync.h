@@ -6,32 +6,14 @@
 
 namespace amq {
 
-// ---------------------------------------------------------------------------
-// Device-wide barrier with bounded waits.
-//   sync[0]: arrival counter (monotone; barrier e completes at e*G arrivals)
-//   sync[1]: last released barrier number
-//   sync[2]: error flag (a wait ran out; every workgroup then exits)
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 only.  Returns false if the wait was abandoned (this wait ran out,
-// or another did and raised the error word `err`).
-__device__ inline bool wait_release(uint32_t *rel, uint32_t *err, uint32_t epoch, uint32_t limit)
+__device__ __forceinline__ void raise_error(uint32_t *err)
 {
-    uint32_t it = 0;
-    while (ld_agent(rel) < epoch) {
-        if (ld_agent(err) != 0u) return false;
-        if (++it > limit) {
-            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
+    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum NV doubles over the workgroup in a fixed order (butterfly in each wave,
@@ -58,68 +40,10 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
     }
 }
 
-// Last group: fixed-order sum of all partial slots into tot[0..NV-1] (LDS).
-// Thread t owns component t % 32 of groups t/32, t/32 + 8, ...; its loads are
-// issued in batches of 4 before any is consumed (one memory round trip per
-// batch of 32 groups), then added in group order.
-template <int NV>
-__device__ void reduce_partials(const double *part, uint32_t G, double *tot, double (*s_red8)[32]);
-
-// Two-level arrival (see the barrier block layout in amq_internal.h).  Group
-// gid stores its partial and arrives at its team's counter; the team's last
-// arriver sums the team's partials in member order into the team slot and
-// arrives at the top counter; the top's last arriver sums the team slots in
-// order into tot (LDS).  Returns, in every thread, whether this group is the
-// top-level last (then tot holds the totals).  At most team-size groups meet
-// on one cache line, and the sums never depend on arrival order.
-template <int NV>
-__device__ inline bool arrive_tree(const double (&v)[NV], uint32_t gid, uint32_t G, double *part,
-                            double *tpart, uint32_t *words, uint32_t epoch, double *tot,
-                            double (*s_red8)[32], int *s_flag)
-{
-    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
-    const uint32_t tau = gid / TS;
-    const uint32_t t_first = tau * TS;
-    const uint32_t t_count = min(TS, G - t_first);
-    if (threadIdx.x == 0) {
-        double *dst = part + (size_t)gid * kPartStride;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) dst[q] = v[q];
-        const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        s_flag[0] = (old + 1u == epoch * t_count) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_flag[0]) return false;
-    reduce_partials<NV>(part + (size_t)t_first * kPartStride, t_count, tot, s_red8);
-    if (threadIdx.x == 0) {
-        double *dst = tpart + (size_t)tau * kPartStride;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) dst[q] = tot[q];
-        const uint32_t old = __hip_atomic_fetch_add(words, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag[0] = (old + 1u == epoch * NT) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_flag[0]) return false;
-    reduce_partials<NV>(tpart, NT, tot, s_red8);
-    return true;
-}
-
-// Top-level last: publish epoch on every team's release line.
-__device__ __forceinline__ void release_all(uint32_t *words, uint32_t G, uint32_t epoch)
-{
-    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    for (uint32_t t = 0; t < NT; ++t)
-        __hip_atomic_store(words + kSyncLine * (1 + kMaxTeams + t), epoch, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t *release_word(uint32_t *words, uint32_t G, uint32_t gid)
-{
-    return words + kSyncLine * (1 + kMaxTeams + gid / team_size(G));
-}
-
+// Fixed-order sum of G partial slots (kPartStride doubles apart) into
+// tot[0..NV-1] (LDS), by the whole workgroup.  Thread t owns component t % 32
+// of groups t/32, t/32 + 8, ...; its loads are issued in batches of 4 before
+// any is consumed, then added in group order.
 template <int NV>
 __device__ void reduce_partials(const double *part, uint32_t G, double *tot, double (*s_red8)[32])
 {
@@ -146,6 +70,126 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
         tot[threadIdx.x] = t;
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide fixed-order sum of NV doubles, every workgroup receiving the
+// total (an all-gather of per-group partials; no group waits on another's
+// release).
+//
+// Each group owns one row of RW 8-byte words in the parity-(epoch & 1) half
+// of `rows` ([2][G][RW]).  Thread 0 stores the group's NV partials there with
+// single-copy-atomic 8-byte stores, the two lowest mantissa bits of each word
+// replaced by epoch & 3 (a change of at most 3 units in the last place, the
+// same in every run), then bumps its team's arrival counter.  Wave 0 polls the
+// team counters until the epoch is complete; then the whole group reads every
+// row (lane c of each RW-lane slice reads word c, all loads of a batch issued
+// before any is used), checks that every word carries this epoch's tag
+// (re-reading if a store had not yet landed: the counter is only a hint, so no
+// store needs to drain before it), and sums in a fixed order: each thread its
+// rows in ascending order, then the lanes and waves of the group in a fixed
+// tree.  Every group computes bitwise the same total.
+//
+// Two parities suffice: a group writes the parity of epoch e + 2 only after
+// epoch e + 1 is complete, and every group finished reading epoch e before
+// publishing its e + 1 row.  A stale word left from epoch e - 2 carries a
+// different tag.  The generation kernel zeroes the rows (tag 0) before each
+// sweep, so words of an earlier sweep never match epochs 1..3, and epoch 4
+// reads words rewritten at epoch 2.
+//
+// Waits are bounded by `limit` polls; on running out, or on seeing the error
+// word raised by another group, returns false (the caller exits).
+// v: valid in thread 0.  tot: LDS [>= NV], valid in every thread on return.
+// ---------------------------------------------------------------------------
+template <int NV, int RW>
+__device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
+                                 uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
+                                 double (*s_red)[32], int *s_flag)
+{
+    static_assert(NV <= RW && RW <= 32 && (RW & (RW - 1)) == 0, "row width");
+    constexpr uint32_t RP = kWG / RW;   // rows per pass
+    constexpr int KB = 16;              // passes per batch (loads in flight per thread)
+    const uint64_t tag = epoch & 3u;
+    uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
+    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
+    if (threadIdx.x == 0) {
+        uint64_t *row = slots + (size_t)gid * RW;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint64_t b = ((uint64_t)__double_as_longlong(v[q]) & ~3ull) | tag;
+            __hip_atomic_store(row + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_fetch_add(words + kSyncLine * (1 + gid / TS), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x < 64) {
+        // lane t < NT watches team t's counter (wave-uniform exit)
+        const uint32_t lane = threadIdx.x;
+        const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
+        uint32_t it = 0;
+        bool ok = true;
+        for (;;) {
+            const uint32_t seen = lane < NT ? ld_agent(words + kSyncLine * (1 + lane)) : 0u;
+            if (__builtin_amdgcn_ballot_w64(seen < want) == 0) break;
+            if (ld_agent(err) != 0u) { ok = false; break; }
+            if (++it > limit) { if (lane == 0) raise_error(err); ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (lane == 0) s_flag[0] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag[0]) return false;
+
+    const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t it = 0;
+    for (;;) {
+        double acc = 0.0;
+        bool bad = false;
+        for (uint32_t r0 = 0; r0 < G; r0 += KB * RP) {
+            uint64_t w[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const uint32_t r = r0 + rs + (uint32_t)k * RP;
+                w[k] = (r < G && c < (uint32_t)NV)
+                           ? __hip_atomic_load(slots + (size_t)r * RW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : tag;
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                bad |= (w[k] & 3u) != tag;
+                acc += __longlong_as_double((long long)(w[k] & ~3ull));
+            }
+        }
+        // lanes c, c + RW, ... of a wave hold the same component
+#pragma unroll
+        for (int o = RW; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        const bool wbad = __builtin_amdgcn_ballot_w64(bad) != 0;
+        if (lane < RW) s_red[wave][lane] = acc;
+        if (lane == 0) s_flag[1 + wave] = wbad ? 1 : 0;
+        __syncthreads();
+        bool anybad = false;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) anybad |= s_flag[1 + q] != 0;
+        if (!anybad) {
+            if (threadIdx.x < NV) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) t += s_red[q][threadIdx.x];
+                tot[threadIdx.x] = t;
+            }
+            __syncthreads();
+            return true;
+        }
+        if (++it > limit) {
+            if (threadIdx.x == 0) raise_error(err);
+            return false;
+        }
+        if (threadIdx.x == 0) s_flag[0] = ld_agent(err) != 0u ? 1 : 0;
+        __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+        if (s_flag[0]) return false;
+    }
 }
 
 }  // namespace amq
