@@ -28,6 +28,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, GB/s
+CSRC = os.path.join(ROOT, "paper_1205_0106_amd", "csrc")
+KERNEL_SOURCES = ("amq_internal.h", "amq_math.h", "amq_sync.h", "amq_sweep.h", "amq_kernels.hip",
+                  "amq_sweep_f32_mono.hip", "amq_sweep_f32_lag.hip", "amq_sweep_f64_mono.hip",
+                  "amq_sweep_f64_lag.hip")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the kernel sources: counter figures taken on other sources
+    are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config: int, dtype: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
+    those runs were taken on other kernel sources, dtype or workload."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if dtype != "fp32" or not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t["kernels"].get(f"cfg{config}:{'sweep_kernel' if kernel == 'sweep' else 'gen_kernel'}")
+    return None if k is None else k["traffic_bytes"]
 
 
 def parse():
@@ -131,7 +160,7 @@ def serve(seconds, dtype):
     return {
         "metric": "p50/p99 solve latency at fixed QPS; served path-steps/s",
         "value": steps / (t_end - t0), "unit": "path-steps/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "f32" if dtype == "fp32" else "f64",
+        "higher_is_better": True, "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64",
         "data": "synthetic (seeded Poisson arrivals and option mix)",
         "config": {"workload": f"serving: Poisson 200 req/s for {seconds:g} s, paths 2^12-2^20, "
                                "dates 12-365, HBM admission budget 64 GB", "requests": len(arr),
@@ -165,7 +194,7 @@ def batch_run(n, dtype, steps, warmup):
     return {"metric": "path-steps/s for QMC-LSM American pricing (batch)",
             "value": total * steps / dt, "unit": "path-steps/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": 1e3 * dt / steps, "higher_is_better": True,
-            "dtype": "f32" if dtype == "fp32" else "f64", "data": "synthetic (seeded option mix)",
+            "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64", "data": "synthetic (seeded option mix)",
             "config": {"workload": f"batch of {n} options: put/call 50/50, K U(80,120), S0 100, "
                                    "sigma U(0.1,0.5), r U(0,0.08), T U(0.25,2), dates U{16..256}, "
                                    "paths 2^14-2^18 log-uniform", "path_steps": total},
@@ -186,13 +215,9 @@ def cpu_baseline(w):
     """The FP64 oracle, single-threaded, on the first paths of the workload."""
     import oracle
     oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
-    # bounded sample, about 10-15 s of single-threaded work
-    if w.n_paths >= (1 << 24):
-        n = 1 << 18
-    elif w.n_paths >= (1 << 20):
-        n = w.n_paths // 2
-    else:
-        n = w.n_paths
+    # bounded sample, about 5-15 s of single-threaded work: the whole
+    # workload up to 2^20 paths, the first 2^19 paths of larger ones
+    n = min(w.n_paths, 1 << 19) if w.n_paths > (1 << 20) else w.n_paths
     kind = oracle.LAGUERRE if w.basis[0] == "laguerre" else oracle.MONOMIAL
     t0 = time.perf_counter()
     r = oracle.price_american(**w.params(), N=n, M=w.n_dates, is_call=w.is_call,
@@ -244,7 +269,7 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(args.config, dtype, dom), "traffic_unit": "HBM bytes per launch",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms, 4)}
 
     out = {
@@ -258,11 +283,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if dtype == "fp32" else "f64",
+        # arithmetic type of the path: binary64 in both modes (FP32 bulk
+        # stores path values and cashflows in binary32, see config.storage)
+        "dtype": "f64",
         "data": "synthetic (on-device Sobol paths)",
         "config": {"workload": w.name, "n_paths": w.n_paths, "n_dates": w.n_dates,
                    "basis": f"{w.basis[0]} degree {w.basis[1]}",
-                   "precision": "FP32 bulk, FP64 solve and sums" if dtype == "fp32" else "FP64",
+                   "storage": "f32" if dtype == "fp32" else "f64",
+                   "precision": ("FP32 bulk: binary32 path values and cashflows, binary32 inverse normal, "
+                                 "binary64 bridge, exponent, regression, solve and sums")
+                   if dtype == "fp32" else "FP64 throughout",
                    "S0": w.S0, "K": w.K, "r": w.r, "sigma": w.sigma, "T": w.T},
         "roofline": roofline,
         "phase_ms": {"generate": round(m["gen_ms"], 4), "sweep": round(m["sweep_ms"], 4)},

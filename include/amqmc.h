@@ -58,10 +58,12 @@ enum { AM_MAX_DEGREE = 6 };
 
 /* Arithmetic of the bulk path data.
  *   AM_FP64:      everything binary64.
- *   AM_FP32_BULK: inverse normal, bridge, paths, basis values and per-thread
- *                 partial sums in binary32 (blocked, carried in binary64);
- *                 cross-thread sums, the normal-equation solve, discount
- *                 factors and the final mean in binary64. */
+ *   AM_FP32_BULK: path values and per-path cashflows stored in binary32
+ *                 (half the HBM traffic and footprint); the inverse normal
+ *                 in binary32; the bridge, the exponent and every step of the
+ *                 backward induction in binary64 on those stored values (the
+ *                 least-squares fit and the exercise test react to relative
+ *                 perturbations near 1e-8 for some options). */
 enum { AM_FP64 = 0, AM_FP32_BULK = 1 };
 
 enum {
