@@ -69,7 +69,7 @@ Layout make_layout(int64_t N, int32_t M, int32_t dtype)
     L.off_S = o;      o = align256(o + (size_t)M * (size_t)L.ld * L.s_bytes);
     L.off_PV = o;     o = align256(o + (size_t)L.ld * L.s_bytes);
     // sweep partial-sum rows [2][G][row words] (also the estimator's partial slots)
-    L.off_part = o;   o = align256(o + (size_t)2 * amq::kMaxGroups * amq::kMaxRowWords * 8);
+    L.off_part = o;   o = align256(o + (size_t)2 * (amq::kMaxGroups + amq::kMaxTeams) * amq::kMaxRowWords * 8);
     L.off_rec = o;    o = align256(o + (size_t)(M + 1) * amq::kRec * 8);
     L.off_datec = o;  o = align256(o + (size_t)(M + 1) * sizeof(amq::DateConst));
     L.off_result = o; o = align256(o + 8 * 8 + amq::kSyncWords * 4);   // result[8], barrier block
@@ -561,7 +561,8 @@ int batch_plan(const am_option *opts, int32_t n, int32_t dtype, BatchPlan &P)
     int64_t max_tiles = 0;
     for (int i = 0; i < n; ++i) max_tiles += P.ld[i] / 256;
     P.off_tiles = o; o = align256(o + (size_t)max_tiles * 4);
-    P.off_part = o;  o = align256(o + (size_t)max_tiles * 2 * amq::kMaxRowWords * 8);   // partial-sum rows
+    // partial-sum rows: per option 2 x (tiles + team rows) x row words
+    P.off_part = o;  o = align256(o + ((size_t)max_tiles + (size_t)n * amq::kMaxTeams) * 2 * amq::kMaxRowWords * 8);
     P.off_units = o; o = align256(o + (size_t)P.max_units * sizeof(amq::GenUnit));
     P.total = o;
     (void)tiles;
@@ -686,6 +687,7 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     std::vector<int32_t> tile_opt;
     int max_G = 0;
     int tiles = 0;
+    size_t rows_off = 0;
     for (int q = 0; q < n_opts; ++q) {
         const int i = P.order[q];
         const am_option &op = opts[i];
@@ -706,8 +708,9 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
         d.M = op.n_dates;
         d.G = (int32_t)((op.n_paths + tile - 1) / tile);
         d.tile_base = tiles;
-        d.rows = (uint64_t *)(ws + P.off_part) + (size_t)tiles * 2 * amq::row_words(basis.degree);
+        d.rows = (uint64_t *)(ws + P.off_part) + rows_off;
         d.rows_n = amq::rows_words(d.G, basis.degree);
+        rows_off += (size_t)d.rows_n;
         d.is_call = op.params.is_call;
         d.allow_exercise = op.params.allow_exercise;
         d.S0 = op.params.S0; d.K = op.params.K; d.r = op.params.r; d.sigma = op.params.sigma;

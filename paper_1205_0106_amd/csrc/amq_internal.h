@@ -28,11 +28,12 @@ constexpr int kSyncWords = kSyncLine * (1 + kMaxTeams);
 __host__ __device__ inline uint32_t team_size(uint32_t G) { return (G + kMaxTeams - 1) / kMaxTeams; }
 
 // Partial-sum rows of one sweep: [2 epoch parities][G][row_words] 8-byte
-// words; each word holds an FP64 partial whose two lowest mantissa bits carry
+// words, then the team rows [2][kMaxTeams][row_words]; each word holds an FP64 partial whose two lowest mantissa bits carry
 // epoch & 3 (see allreduce in amq_sync.h).  Zeroed by the generation kernel.
 __host__ __device__ constexpr int row_words(int degree) { return 3 * degree + 3 <= 16 ? 16 : 32; }
 constexpr int kMaxRowWords = 32;
-__host__ __device__ inline int64_t rows_words(int64_t G, int degree) { return 2 * G * row_words(degree); }
+// group rows [2][G][row_words] then team rows [2][kMaxTeams][row_words]
+__host__ __device__ inline int64_t rows_words(int64_t G, int degree) { return 2 * (G + kMaxTeams) * row_words(degree); }
 constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
 
 // One node of the Brownian bridge, in depth-first construction order.  The

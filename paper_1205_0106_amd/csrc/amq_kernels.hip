@@ -257,8 +257,9 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     const int offL = gl & 7, offH = 8 + (gl >> 3);
     const int xsel = lane == 63 ? 1 : 0;
 
-    // The bridge and the exponent run in binary64 for both storage types;
-    // binary32 storage rounds the binary64 value once (the exercise decisions
+    // The bridge and the exponent run in binary64 for both storage types
+    // (binary32 storage: an exponential good to 3e-10, rounded once to
+    // binary32; the exercise decisions
     // downstream are sensitive to path-value errors well below a binary32 ulp,
     // so nothing but the final rounding is left in binary32).  Only the
     // inverse normal is evaluated in the storage precision.
@@ -301,7 +302,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             const double wv = nd.wl * W[nd.sl] + nd.wr * W[nd.sr] + nd.sd * (double)z;
             W[nd.dst] = wv;
             const double e = mu * (double)nd.m + vol * wv;
-            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly(e) : exp(e)));
+            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp(e)));
             ((T *)a.S)[(size_t)(nd.m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {

@@ -31,4 +31,43 @@ __device__ __forceinline__ double exp_poly(double x)
     return ldexp(p, (int)n);
 }
 
+// exp(x) to about 1e-10 relative, for values that are then rounded to
+// binary32 (0.003 of a binary32 ulp): the same reduction with a degree-8
+// Taylor polynomial (truncation below 0.3466^9 / 9! < 2.1e-10).
+__device__ __forceinline__ double exp_poly_f32(double x)
+{
+    const double n = rint(x * 1.4426950408889634);
+    const double g = fma(-n, 2.3190468138462996e-17, fma(-n, 0.69314718055994529, x));
+    double p = 1.0 / 40320.0;                      // 1/8!
+    p = fma(p, g, 1.0 / 5040.0);
+    p = fma(p, g, 1.0 / 720.0);
+    p = fma(p, g, 1.0 / 120.0);
+    p = fma(p, g, 1.0 / 24.0);
+    p = fma(p, g, 1.0 / 6.0);
+    p = fma(p, g, 0.5);
+    p = fma(p, g, 1.0);
+    p = fma(p, g, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// 1/sqrt(d) and 1/d for d > 0 in binary64: hardware estimate refined by
+// Newton steps (each roughly doubles the correct bits; two from the ~2^-22
+// estimate reach full binary64 precision).
+__device__ __forceinline__ double rsqrt_f64(double d)
+{
+    double y = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    y = y * fma(-hd * y, y, 1.5);
+    y = y * fma(-hd * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double rcp_f64(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    y = y * fma(-d, y, 2.0);
+    y = y * fma(-d, y, 2.0);
+    return y;
+}
+
 }  // namespace amq

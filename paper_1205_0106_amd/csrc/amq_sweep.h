@@ -11,46 +11,56 @@ namespace amq {
 
 // FP64 normal-equation solve for the p = D+1 coefficients from Hankel moments
 // tot[0..2D] (sum of wA xs^q), tot[2D+1 .. 3D+1] (sum of wB xs^a pv) and the
-// in-the-money count tot[3D+2].  Equilibrated Cholesky by one thread, with
-// the factor and work vectors in LDS (registers here would be allocated in
-// every lane beside the resident cashflows); a date with fewer in-the-money
+// in-the-money count tot[3D+2].  Equilibrated Cholesky by one thread; L and
+// w are registers where the kernel has room (registers are allocated in
+// every lane, beside the resident cashflows), else LDS; a date with fewer in-the-money
 // paths than p or a pivot below 1e-14 (on the unit-diagonal matrix) allows no
 // exercise.  beta: [0..7] coefficients in the standardised basis (zero past
 // p), [8] solved flag, [9] in-the-money count.
 template <int D>
-__device__ void solve_date(const double *tot, double *beta, double (*L)[8], double *w)
+__device__ __forceinline__ void solve_date(const double *tot, double *beta, double (*L)[8], double *w)
 {
     constexpr int P = D + 1, NA = 2 * D + 1;
     const double n = rint(tot[NA + P]);
     bool ok = n >= (double)P;
     double *sc = w, *rl = w + 8, *y = w + 16, *gam = w + 24;
+#pragma unroll
     for (int i = 0; i < P; ++i) {
         const double d = tot[2 * i];
         ok = ok && (d > 0.0);
-        sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        sc[i] = d > 0.0 ? rsqrt_f64(d) : 0.0;
     }
+#pragma unroll
     for (int j = 0; j < P; ++j) {
         double d = tot[2 * j] * sc[j] * sc[j];
+#pragma unroll
         for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
         ok = ok && (d > 1e-14);
-        rl[j] = 1.0 / (d > 1e-14 ? sqrt(d) : 1.0);
+        rl[j] = d > 1e-14 ? rsqrt_f64(d) : 1.0;    // 1 / L[j][j]
+#pragma unroll
         for (int i = j + 1; i < P; ++i) {
             double e = tot[i + j] * sc[i] * sc[j];
+#pragma unroll
             for (int l = 0; l < j; ++l) e -= L[i][l] * L[j][l];
             L[i][j] = e * rl[j];
         }
     }
+#pragma unroll
     for (int i = 0; i < P; ++i) {
         double e = tot[NA + i] * sc[i];
+#pragma unroll
         for (int l = 0; l < i; ++l) e -= L[i][l] * y[l];
         y[i] = e * rl[i];
     }
+#pragma unroll
     for (int i = P - 1; i >= 0; --i) {
         double e = y[i];
+#pragma unroll
         for (int l = i + 1; l < P; ++l) e -= L[l][i] * gam[l];
         gam[i] = e * rl[i];
     }
-    for (int i = 0; i < 8; ++i) beta[i] = (i < P && ok) ? gam[i] * sc[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) beta[i] = (i < P && ok) ? gam[i < P ? i : 0] * sc[i < P ? i : 0] : 0.0;
     beta[8] = ok ? 1.0 : 0.0;
     beta[9] = n;
 }
@@ -96,7 +106,7 @@ struct SweepShape {
 // Adds path value s (cashflow pvj discounted to t0) to the in-the-money
 // moments acc[0..NA-1] (sum of wA xs^q) and acc[NA..NA+NB-1] (sum of wB xs^q
 // pvj); returns 1 if the path is in the money.
-template <int D, bool LAG>
+template <int D, bool LAG, bool PIN = true>
 __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double K, bool call, double xa,
                                            double xb, double wc)
 {
@@ -121,9 +131,28 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
     // pin the accumulators here: without this the optimizer sinks the sums
     // of a whole unrolled run of paths to its end, keeping every path's
     // powers live at once
+    if (PIN) {
 #pragma unroll
-    for (int q = 0; q < NA + NB; ++q) asm volatile("" : "+v"(acc[q]));
+        for (int q = 0; q < NA + NB; ++q) asm volatile("" : "+v"(acc[q]));
+    }
     return itm ? 1 : 0;
+}
+
+// Two paths into two accumulator sets (independent dependency chains for the
+// scheduler), pinned together; the sets are added at the end of the pass.
+template <int D, bool LAG>
+__device__ __forceinline__ int moments_add2(double *acc, double *acc2, double s0, double pv0, double s1,
+                                            double pv1, double K, bool call, double xa, double xb, double wc)
+{
+    constexpr int NA = 2 * D + 1, NB = D + 1;
+    const int c = moments_add<D, LAG, false>(acc, s0, pv0, K, call, xa, xb, wc) +
+                  moments_add<D, LAG, false>(acc2, s1, pv1, K, call, xa, xb, wc);
+#pragma unroll
+    for (int q = 0; q < NA + NB; ++q) {
+        asm volatile("" : "+v"(acc[q]));
+        asm volatile("" : "+v"(acc2[q]));
+    }
+    return c;
 }
 
 // Exercise update at a date: exercise (cashflow dk h) when in the money and
@@ -239,14 +268,22 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         int cnt = 0;
         if (KEEP) {
+            // path pairs: two independent chains per step (one wave per SIMD
+            // at a group per CU leaves the binary64 latencies to ILP)
+            double acc2[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc2[q] = 0.0;
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    cnt += moments_add<D, LAG>(acc, (double)sc[jj].v[e], (double)pv[jj * VW + e], K, call, xa, xb, wc);
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int e = 0; e < VW; e += 2) {
+                    cnt += moments_add2<D, LAG>(acc, acc2, (double)sc[jj].v[e], (double)pv[jj * VW + e],
+                                                (double)sc[jj].v[e + 1], (double)pv[jj * VW + e + 1], K, call,
+                                                xa, xb, wc);
                 }
             }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[q] += acc2[q];
         } else {
             Vec<T> ring[PD];
 #pragma unroll
@@ -283,7 +320,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         }
         if (tid == 0) {
             const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
-            solve_date<D>(s_tot, s_beta, s_L, s_w);
+            if constexpr (KEEP) {
+                double Lr[8][8], wr[32];
+                solve_date<D>(s_tot, s_beta, Lr, wr);
+            } else {
+                solve_date<D>(s_tot, s_beta, s_L, s_w);
+            }
             if (gid == 0) {
                 // every group solved the same system; group 0 keeps the record
                 double *rec = a.rec + (size_t)k * kRec;
@@ -305,11 +347,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 #pragma unroll
                 for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) {
+                    for (int e = 0; e < VW; ++e)
                         pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], K, call, xa,
                                                                      xb, dk, gam, wc);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
                 }
             } else {
                 Vec<T> ring[PD];

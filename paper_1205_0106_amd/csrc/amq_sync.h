@@ -90,6 +90,12 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
 // rows in ascending order, then the lanes and waves of the group in a fixed
 // tree.  Every group computes bitwise the same total.
 //
+// Above kFlatMaxGroups groups (every group reading every row would move
+// G^2 rows per date), the last arriver of each team (from its counter's
+// return value) first sums its team's rows in member order into a tagged
+// team row; every group then polls the team rows' tags and sums the team
+// rows in team order.
+//
 // Two parities suffice: a group writes the parity of epoch e + 2 only after
 // epoch e + 1 is complete, and every group finished reading epoch e before
 // publishing its e + 1 row.  A stale word left from epoch e - 2 carries a
@@ -101,57 +107,29 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
 // word raised by another group, returns false (the caller exits).
 // v: valid in thread 0.  tot: LDS [>= NV], valid in every thread on return.
 // ---------------------------------------------------------------------------
+// Fixed-order sum of rows [0, count) of `slots` (RW words each, tagged):
+// lane c of each RW-lane slice reads word c, KB rows per thread in flight;
+// every word must carry `tag`, else the rows are read again (bounded).  Each
+// thread adds its rows in ascending order, then the group's lanes and waves
+// in a fixed tree.  tot: LDS [>= NV], valid in every thread on true.
 template <int NV, int RW>
-__device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
-                                 uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
-                                 double (*s_red)[32], int *s_flag)
+__device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t tag, uint32_t *err,
+                                uint32_t limit, double *tot, double (*s_red)[32], int *s_flag)
 {
-    static_assert(NV <= RW && RW <= 32 && (RW & (RW - 1)) == 0, "row width");
     constexpr uint32_t RP = kWG / RW;   // rows per pass
     constexpr int KB = 16;              // passes per batch (loads in flight per thread)
-    const uint64_t tag = epoch & 3u;
-    uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
-    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
-    if (threadIdx.x == 0) {
-        uint64_t *row = slots + (size_t)gid * RW;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const uint64_t b = ((uint64_t)__double_as_longlong(v[q]) & ~3ull) | tag;
-            __hip_atomic_store(row + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __hip_atomic_fetch_add(words + kSyncLine * (1 + gid / TS), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x < 64) {
-        // lane t < NT watches team t's counter (wave-uniform exit)
-        const uint32_t lane = threadIdx.x;
-        const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
-        uint32_t it = 0;
-        bool ok = true;
-        for (;;) {
-            const uint32_t seen = lane < NT ? ld_agent(words + kSyncLine * (1 + lane)) : 0u;
-            if (__builtin_amdgcn_ballot_w64(seen < want) == 0) break;
-            if (ld_agent(err) != 0u) { ok = false; break; }
-            if (++it > limit) { if (lane == 0) raise_error(err); ok = false; break; }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (lane == 0) s_flag[0] = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_flag[0]) return false;
-
     const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t it = 0;
     for (;;) {
         double acc = 0.0;
         bool bad = false;
-        for (uint32_t r0 = 0; r0 < G; r0 += KB * RP) {
+        for (uint32_t r0 = 0; r0 < count; r0 += KB * RP) {
             uint64_t w[KB];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
                 const uint32_t r = r0 + rs + (uint32_t)k * RP;
-                w[k] = (r < G && c < (uint32_t)NV)
+                w[k] = (r < count && c < (uint32_t)NV)
                            ? __hip_atomic_load(slots + (size_t)r * RW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                            : tag;
             }
@@ -190,6 +168,81 @@ __device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G
         __syncthreads();
         if (s_flag[0]) return false;
     }
+}
+
+// Thread 0: store the NV values as a tagged row (single-copy-atomic words).
+template <int NV>
+__device__ __forceinline__ void put_row(uint64_t *row, const double *v, uint64_t tag)
+{
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const uint64_t b = ((uint64_t)__double_as_longlong(v[q]) & ~3ull) | tag;
+        __hip_atomic_store(row + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Groups at or below this count read every group's row; above it, teams sum
+// first (see allreduce).
+constexpr uint32_t kFlatMaxGroups = 256;
+
+template <int NV, int RW>
+__device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
+                                 uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
+                                 double (*s_red)[32], int *s_flag)
+{
+    static_assert(NV <= RW && RW <= 32 && (RW & (RW - 1)) == 0, "row width");
+    const uint64_t tag = epoch & 3u;
+    uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
+    uint64_t *tslots = rows + (size_t)2 * G * RW + (size_t)(epoch & 1u) * kMaxTeams * RW;
+    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
+    const uint32_t tau = gid / TS;
+    const bool flat = G <= kFlatMaxGroups;
+    if (threadIdx.x == 0) {
+        put_row<NV>(slots + (size_t)gid * RW, v, tag);
+        const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        s_flag[0] = (!flat && old + 1u == epoch * min(TS, G - tau * TS)) ? 1 : 0;   // team's last arrival
+    }
+    if (!flat) {
+        // team level: the team's last arriver sums its team's rows in member
+        // order and publishes the team row (tagged like the group rows)
+        __syncthreads();
+        if (s_flag[0]) {
+            const uint32_t first = tau * TS;
+            if (!sum_rows<NV, RW>(slots + (size_t)first * RW, min(TS, G - first), tag, err, limit, tot, s_red,
+                                  s_flag))
+                return false;
+            if (threadIdx.x == 0) put_row<NV>(tslots + (size_t)tau * RW, tot, tag);
+        }
+    }
+    if (threadIdx.x < 64) {
+        // flat: lane t < NT watches team t's counter; teams: lane t watches
+        // team t's row (word 0 carries the epoch tag).  Wave-uniform exit.
+        const uint32_t lane = threadIdx.x;
+        const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
+        uint32_t it = 0;
+        bool ok = true;
+        for (;;) {
+            bool pending;
+            if (flat) {
+                const uint32_t seen = lane < NT ? ld_agent(words + kSyncLine * (1 + lane)) : 0u;
+                pending = seen < want;
+            } else {
+                const uint64_t w0 = lane < NT ? __hip_atomic_load(tslots + (size_t)lane * RW, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT)
+                                              : tag;
+                pending = (w0 & 3u) != tag;
+            }
+            if (__builtin_amdgcn_ballot_w64(pending) == 0) break;
+            if (ld_agent(err) != 0u) { ok = false; break; }
+            if (++it > limit) { if (lane == 0) raise_error(err); ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (lane == 0) s_flag[0] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag[0]) return false;
+    return sum_rows<NV, RW>(flat ? slots : tslots, flat ? G : NT, tag, err, limit, tot, s_red, s_flag);
 }
 
 }  // namespace amq

@@ -215,6 +215,20 @@ def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
         assert abs(price - ores.price) <= 0.02 * ores.price + TOL[dtype]
 
 
+def test_team_level_device_sum(amq, orc, pricer):
+    # more than 256 workgroups: teams sum first; 500 groups of 64 paths per
+    # thread leaves a last team of 4 (teams of 16)
+    N, M = 500 * 256 * 64 - 7, 4
+    kw = dict(S0=100.0, K=105.0, r=0.04, sigma=0.25, T=0.75)
+    price, se, v = gpu_price(amq, pricer, None, N=N, M=M, dtype="fp64", basis=("monomial", 2), **kw)
+    ores, od = oracle_price(orc, None, N=N, M=M, basis=("monomial", 2), **kw)
+    nitm = v["rec"].cpu().numpy()[1:M, 9].astype(np.int64)
+    log(f"  N={N}: gpu {price:.10f} oracle {ores.price:.10f}; itm {nitm} vs {od['nitm'][1:M]}")
+    assert np.array_equal(nitm, od["nitm"][1:M])
+    assert abs(price - ores.price) <= TOL["fp64"]
+    assert abs(se - ores.std_err) <= 1e-6 * ores.std_err
+
+
 @pytest.mark.parametrize("call,K", [(False, 100.59555281085481), (True, 80.14936968208303),
                                     (False, 97.3), (True, 113.1)])
 def test_fp32_padding_stays_out_of_the_money(amq, orc, pricer, call, K):
