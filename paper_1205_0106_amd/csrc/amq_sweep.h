@@ -108,7 +108,7 @@ struct SweepShape {
 // pvj); returns 1 if the path is in the money.
 template <int D, bool LAG, bool PIN = true>
 __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double K, bool call, double xa,
-                                           double xb, double wc)
+                                           double xb, double wc, double *wout = nullptr)
 {
     constexpr int NA = 2 * D + 1, NB = D + 1;
     const double h = call ? s - K : K - s;
@@ -117,6 +117,7 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
     double wA = 1.0, wB = 1.0;
     if (LAG) {
         const double w = lag_weight(s, wc);
+        if (wout) *wout = w;
         wA = w * w;
         wB = w;
     }
@@ -142,11 +143,12 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
 // scheduler), pinned together; the sets are added at the end of the pass.
 template <int D, bool LAG>
 __device__ __forceinline__ int moments_add2(double *acc, double *acc2, double s0, double pv0, double s1,
-                                            double pv1, double K, bool call, double xa, double xb, double wc)
+                                            double pv1, double K, bool call, double xa, double xb, double wc,
+                                            double *w0, double *w1)
 {
     constexpr int NA = 2 * D + 1, NB = D + 1;
-    const int c = moments_add<D, LAG, false>(acc, s0, pv0, K, call, xa, xb, wc) +
-                  moments_add<D, LAG, false>(acc2, s1, pv1, K, call, xa, xb, wc);
+    const int c = moments_add<D, LAG, false>(acc, s0, pv0, K, call, xa, xb, wc, w0) +
+                  moments_add<D, LAG, false>(acc2, s1, pv1, K, call, xa, xb, wc, w1);
 #pragma unroll
     for (int q = 0; q < NA + NB; ++q) {
         asm volatile("" : "+v"(acc[q]));
@@ -159,7 +161,7 @@ __device__ __forceinline__ int moments_add2(double *acc, double *acc2, double s0
 // dk h exceeds the fitted continuation; else keep pvj.
 template <typename T, int D, bool LAG>
 __device__ __forceinline__ T exercise_update(T s_t, T pvj, double K, bool call, double xa, double xb, double dk,
-                                             const double *gam, double wc)
+                                             const double *gam, double wc, const double *wgiven = nullptr)
 {
     constexpr int P = D + 1;
     const double s = (double)s_t;
@@ -168,7 +170,7 @@ __device__ __forceinline__ T exercise_update(T s_t, T pvj, double K, bool call, 
     double cont = gam[P - 1];
 #pragma unroll
     for (int q = P - 2; q >= 0; --q) cont = fma(cont, xs, gam[q]);
-    if (LAG) cont *= lag_weight(s, wc);
+    if (LAG) cont *= wgiven ? *wgiven : lag_weight(s, wc);
     const double ex = dk * h;
     return (h > 0.0 && ex > cont) ? (T)ex : pvj;
 }
@@ -199,7 +201,7 @@ template <typename T, int PPT, int D, bool LAG>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                            uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                            double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
-                                           double *s_w, int *s_flag)
+                                           double *s_w, double *s_wl, DateConst *s_dc, int *s_flag)
 {
     using SH = SweepShape<T, PPT>;
     constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
@@ -258,9 +260,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 #pragma unroll
         for (int jj = 0; jj < NVEC; ++jj) sc[jj] = vload(row, jj);
     }
+    // date constants staged in LDS (a dependent global load at the top of
+    // each date would stall the moment pass)
+    for (int k = tid; k <= a.M; k += kWG) s_dc[k] = a.datec[k];
+    __syncthreads();
     for (int k = a.M - 1; k >= 1; --k) {
-        const DateConst dc = a.datec[k];
-        const double xa = dc.xa, xb = dc.xb, dk = dc.disc;
+        const double xa = uniform_f64(s_dc[k].xa), xb = uniform_f64(s_dc[k].xb),
+                     dk = uniform_f64(s_dc[k].disc);
         const T *row = S + (size_t)(k - 1) * ld;
 
         double acc[NV];
@@ -277,9 +283,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
             for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
                 for (int e = 0; e < VW; e += 2) {
-                    cnt += moments_add2<D, LAG>(acc, acc2, (double)sc[jj].v[e], (double)pv[jj * VW + e],
-                                                (double)sc[jj].v[e + 1], (double)pv[jj * VW + e + 1], K, call,
-                                                xa, xb, wc);
+                    const int j0 = jj * VW + e;
+                    cnt += moments_add2<D, LAG>(acc, acc2, (double)sc[jj].v[e], (double)pv[j0],
+                                                (double)sc[jj].v[e + 1], (double)pv[j0 + 1], K, call, xa, xb,
+                                                wc, LAG ? &s_wl[j0 * kWG + tid] : nullptr,
+                                                LAG ? &s_wl[(j0 + 1) * kWG + tid] : nullptr);
                 }
             }
 #pragma unroll
@@ -349,7 +357,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
                         pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], K, call, xa,
-                                                                     xb, dk, gam, wc);
+                                                                     xb, dk, gam, wc,
+                                                                     LAG ? &s_wl[(jj * VW + e) * kWG + tid] : nullptr);
+                    __builtin_amdgcn_sched_barrier(0);   // one vector's paths at a time
                 }
             } else {
                 Vec<T> ring[PD];
@@ -466,6 +476,10 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
     __shared__ double s_beta[10];
     __shared__ double s_L[8][8];
     __shared__ double s_w[32];
+    // Laguerre weights of a KEEP tile, [path][thread], between the moment
+    // pass and the exercise update of a date
+    __shared__ double s_wl[LAG && SweepShape<T, PPT>::KEEP ? PPT * kWG : 1];
+    __shared__ DateConst s_dc[kMaxDates + 1];
     __shared__ int s_flag[1 + kWaves];
 
     const uint32_t gid = blockIdx.x;
@@ -473,7 +487,8 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
     T pv[PPT];
     uint32_t epoch = 0;
     bool alive = true;
-    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w, s_flag);
+    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w, s_wl, s_dc,
+                               s_flag);
     if (!alive) return;
     sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
 }
@@ -488,6 +503,10 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
     __shared__ double s_beta[10];
     __shared__ double s_L[8][8];
     __shared__ double s_w[32];
+    // Laguerre weights of a KEEP tile, [path][thread], between the moment
+    // pass and the exercise update of a date
+    __shared__ double s_wl[LAG && SweepShape<T, PPT>::KEEP ? PPT * kWG : 1];
+    __shared__ DateConst s_dc[kMaxDates + 1];
     __shared__ int s_flag[1 + kWaves];
     __shared__ int s_claim;
 
@@ -525,7 +544,7 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
         uint32_t epoch = 0;
         bool alive = true;
         sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w,
-                                   s_flag);
+                                   s_wl, s_dc, s_flag);
         if (!alive) return;
         sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
     }

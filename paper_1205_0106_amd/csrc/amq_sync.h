@@ -11,25 +11,56 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A wave-uniform binary64 value moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void raise_error(uint32_t *err)
 {
     __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum NV doubles over the workgroup in a fixed order (butterfly in each wave,
+// x + (the value DPP control `CTRL` moves into this lane, in the rows of
+// ROW_MASK; +0 in the other rows).  binary64 through two 32-bit DPP moves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return x + __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum of x over the 64 lanes of a wave, valid in lane 63, in a fixed order
+// on the vector unit (DPP, no LDS round trips): neighbour swaps within quads,
+// the half-row and row mirrors (every lane of a 16-lane row then holds the
+// row sum), then row 0 into row 1 and row 2 into row 3 (row_bcast:15), and
+// lane 31 into rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+    x = dpp_add<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+    x = dpp_add<0x141, 0xF>(x);   // row_half_mirror
+    x = dpp_add<0x140, 0xF>(x);   // row_mirror
+    x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Sum NV doubles over the workgroup in a fixed order (wave_sum in each wave,
 // then waves 0..3 in order).  Result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double x = v[q];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-        v[q] = x;
-    }
-    if (lane == 0) {
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) s_red[wave][q] = v[q];
     }
