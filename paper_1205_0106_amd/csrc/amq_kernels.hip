@@ -322,8 +322,10 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     }
 }
 
+// four waves per SIMD (at most 128 VGPRs): latency hiding for the per-lane
+// dependency chain of each path through the dates
 template <typename T, int WHAT, bool MID>
-__global__ void __launch_bounds__(kWG)
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
 gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
            const uint32_t *__restrict__ shift)
 {
@@ -438,7 +440,7 @@ __device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kWG)
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
 gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ units,
                  const uint32_t *__restrict__ V, uint32_t *gsync)
 {

@@ -52,6 +52,27 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+// x(row 2i) + x(row 2i+1) in every lane of both rows (16-lane rows), and
+// x(lane l mod 32) + x(lane l mod 32 + 32): gfx950's row-swapping permutes
+// (v_permlane16_swap / v_permlane32_swap), lower operand first in every lane.
+__device__ __forceinline__ double add_rows16(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
+__device__ __forceinline__ double add_halves32(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
 // Sum NV doubles over the workgroup in a fixed order (wave_sum in each wave,
 // then waves 0..3 in order).  Result valid in thread 0.
 template <int NV>
@@ -147,6 +168,7 @@ template <int NV, int RW>
 __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t tag, uint32_t *err,
                                 uint32_t limit, double *tot, double (*s_red)[32], int *s_flag)
 {
+    static_assert(RW == 16 || RW == 32, "row width");
     constexpr uint32_t RP = kWG / RW;   // rows per pass
     constexpr int KB = 16;              // passes per batch (loads in flight per thread)
     const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
@@ -171,8 +193,8 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
             }
         }
         // lanes c, c + RW, ... of a wave hold the same component
-#pragma unroll
-        for (int o = RW; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (RW == 16) acc = add_rows16(acc);
+        acc = add_halves32(acc);
         const bool wbad = __builtin_amdgcn_ballot_w64(bad) != 0;
         if (lane < RW) s_red[wave][lane] = acc;
         if (lane == 0) s_flag[1 + wave] = wbad ? 1 : 0;
