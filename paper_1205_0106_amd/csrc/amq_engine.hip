@@ -725,14 +725,19 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     const int grid = tiles < capacity ? tiles : capacity;
     if (max_G > grid)
         return fail(AM_EDIM, "an option needs %d tiles but only %d workgroups are resident", max_G, grid);
-    // generation units: waves of R blocks, about 32 waves per CU in total
+    // generation units: about 32 waves per CU in total, each wave given about
+    // the same number of path-steps (blocks x dates), so options with many
+    // dates get fewer blocks per wave and no unit outlasts the rest
     const int64_t target_waves = (int64_t)st->num_cu * 32;
-    int64_t R = (P.total_blocks + target_waves - 1) / target_waves;
-    if (R < 1) R = 1;
+    int64_t total_work = 0;
+    for (int i = 0; i < n_opts; ++i) total_work += (P.ld[i] / 64) * (int64_t)opts[i].n_dates;
+    const int64_t wave_work = (total_work + target_waves - 1) / target_waves;
     std::vector<amq::GenUnit> units;
     for (int q = 0; q < n_opts; ++q) {
         const int i = P.order[q];
         const int64_t nb = P.ld[i] / 64;
+        int64_t R = (wave_work + opts[i].n_dates / 2) / opts[i].n_dates;
+        if (R < 1) R = 1;
         for (int64_t b = 0; b < nb; b += amq::kWaves * R) {
             amq::GenUnit u;
             u.opt = i; u.pad = 0; u.b0 = b; u.b1 = b + amq::kWaves * R < nb ? b + amq::kWaves * R : nb;

@@ -286,8 +286,16 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             continue;
         }
         for (int s = 0; s < M; ++s) {
-            const BridgeNode nd = sched[s];
-            const int j = nd.dim;
+            // node fields moved to scalar registers: the batch kernel reaches
+            // the schedule through a loaded descriptor, and a window index the
+            // compiler cannot prove uniform turns every slot access into a
+            // compare-and-select chain
+            const BridgeNode &nd = sched[s];
+            const int j = __builtin_amdgcn_readfirstlane(nd.dim);
+            const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
+            const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl), n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
+                      n_dst = __builtin_amdgcn_readfirstlane(nd.dst);
+            const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr), n_sd = uniform_f64(nd.sd);
             uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
             if (MID) x ^= shift[j];
             if (WHAT == 1) {
@@ -299,11 +307,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = (double)z;
                 continue;
             }
-            const double wv = nd.wl * W[nd.sl] + nd.wr * W[nd.sr] + nd.sd * (double)z;
-            W[nd.dst] = wv;
-            const double e = mu * (double)nd.m + vol * wv;
+            const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
+            W[n_dst] = wv;
+            const double e = mu * (double)n_m + vol * wv;
             const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp(e)));
-            ((T *)a.S)[(size_t)(nd.m - 1) * a.ld + i] = valid ? Sv : Kp;
+            ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {
             const int c = min(__builtin_ctzll((uint64_t)w + 2u) + 6, 31);
