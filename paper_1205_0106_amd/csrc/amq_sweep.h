@@ -114,21 +114,21 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
     const double h = call ? s - K : K - s;
     const bool itm = h > 0.0;
     const double xs = fma(s, xa, xb);
-    double wA = 1.0, wB = 1.0;
+    double w = 1.0;
     if (LAG) {
-        const double w = lag_weight(s, wc);
+        w = lag_weight(s, wc);
         if (wout) *wout = w;
-        wA = w * w;
-        wB = w;
     }
-    double pa = itm ? wA : 0.0;
-    acc[0] += pa;
+    // y_q = w xs^q on an in-the-money path (0 otherwise): the Gram moments
+    // are sum w y_q (w = 1: sum y_q) and the right-hand side sum pvj y_q, so
+    // one product chain serves both
+    double y = itm ? w : 0.0;
 #pragma unroll
-    for (int q = 1; q < NA; ++q) { pa *= xs; acc[q] += pa; }
-    double pb = itm ? wB * pvj : 0.0;
-    acc[NA] += pb;
-#pragma unroll
-    for (int q = 1; q < NB; ++q) { pb *= xs; acc[NA + q] += pb; }
+    for (int q = 0; q < NA; ++q) {
+        acc[q] = LAG ? fma(w, y, acc[q]) : acc[q] + y;
+        if (q < NB) acc[NA + q] = fma(pvj, y, acc[NA + q]);
+        if (q + 1 < NA) y *= xs;
+    }
     // pin the accumulators here: without this the optimizer sinks the sums
     // of a whole unrolled run of paths to its end, keeping every path's
     // powers live at once
@@ -518,7 +518,9 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
             s_claim = t;
         }
         __syncthreads();
-        const int t = s_claim;
+        // (wave-uniform: the descriptor and everything derived from it then
+        // live in scalar registers)
+        const int t = __builtin_amdgcn_readfirstlane(s_claim);
         if (t >= g.total_tiles) return;
         const BatchOpt o = opts[tile_opt[t]];
         SweepArgs a;
