@@ -398,6 +398,24 @@ int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree)
     return blocks_per_cu(sweep_lookup(fp64, laguerre, ppt, degree, 1));
 }
 
+// Dynamic LDS that leaves room for one workgroup of `f` per CU (more than
+// half of a CU's LDS in total), so a grid of at most one group per CU is
+// spread over the CUs instead of doubling up on some; 0 if unavailable.
+static size_t one_per_cu_lds(const void *f)
+{
+    int dev = 0, lds_cu = 0;
+    hipFuncAttributes fa;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa, f) != hipSuccess)
+        return 0;
+    const size_t want = (size_t)lds_cu / 2 + 1024;
+    if (fa.sharedSizeBytes >= want) return 0;
+    const size_t dyn = want - fa.sharedSizeBytes;
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) return 0;
+    return dyn;
+}
+
 hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
 {
     const void *f = sweep_lookup(fp64, a.laguerre, ppt, a.degree, 0);
@@ -405,7 +423,12 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
     SweepArgs args = a;
     const void *Sp = a.S;
     void *params[] = {(void *)&args, (void *)&Sp};
-    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3(kWG), params, 0, s);
+    int dev = 0, cus = 0;
+    size_t dyn = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && a.G <= cus)
+        dyn = one_per_cu_lds(f);
+    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3(kWG), params, (unsigned)dyn, s);
 }
 
 // ---------------------------------------------------------------------------

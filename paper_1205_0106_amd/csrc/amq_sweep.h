@@ -93,8 +93,11 @@ struct SweepShape {
     static constexpr bool KEEP = sizeof(T) * PPT <= 64;
     // STREAM (not KEEP): ring of PD vectors in flight per thread.
     static constexpr int PD = NVEC < 8 ? NVEC : 8;
-    // register budget: STREAM kernels run 2 waves per SIMD (256 VGPRs)
-    static constexpr int WAVES = KEEP ? 2 : 2;
+    // register budget: waves per SIMD the kernel is compiled for (256
+    // VGPRs at 2; the smallest monomial tiles of degree <= 2 fit 4 groups
+    // per CU at 128)
+    template <int D, bool LAG>
+    static constexpr int waves() { return (sizeof(T) * PPT <= 16 && !LAG && D <= 2) ? 4 : 2; }
 };
 
 // The per-path arithmetic of the sweep is binary64 for both storage types
@@ -103,22 +106,24 @@ struct SweepShape {
 // there moves some prices by more than the binary32 tolerance.  On gfx950
 // without packed binary32 math a binary64 FMA issues at the binary32 rate.
 
+// Signed payoff argument h = sg (s - K) with sg = +1 (call) or -1 (put) and
+// nsk = -sg K: one fma, exactly the rounded s - K or K - s.
+__device__ __forceinline__ double payoff_arg(double s, double sg, double nsk)
+{
+    return fma(sg, s, nsk);
+}
+
 // Adds path value s (cashflow pvj discounted to t0) to the in-the-money
 // moments acc[0..NA-1] (sum of wA xs^q) and acc[NA..NA+NB-1] (sum of wB xs^q
-// pvj); returns 1 if the path is in the money.
+// pvj); returns 1 if the path is in the money.  (Streamed tiles: one pass.)
 template <int D, bool LAG, bool PIN = true>
-__device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double K, bool call, double xa,
-                                           double xb, double wc, double *wout = nullptr)
+__device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double sg, double nsk, double xa,
+                                           double xb, double wc)
 {
     constexpr int NA = 2 * D + 1, NB = D + 1;
-    const double h = call ? s - K : K - s;
-    const bool itm = h > 0.0;
+    const bool itm = payoff_arg(s, sg, nsk) > 0.0;
     const double xs = fma(s, xa, xb);
-    double w = 1.0;
-    if (LAG) {
-        w = lag_weight(s, wc);
-        if (wout) *wout = w;
-    }
+    const double w = LAG ? lag_weight(s, wc) : 1.0;
     // y_q = w xs^q on an in-the-money path (0 otherwise): the Gram moments
     // are sum w y_q (w = 1: sum y_q) and the right-hand side sum pvj y_q, so
     // one product chain serves both
@@ -139,40 +144,68 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
     return itm ? 1 : 0;
 }
 
-// Two paths into two accumulator sets (independent dependency chains for the
-// scheduler), pinned together; the sets are added at the end of the pass.
+// The same sums split in two for register-resident tiles: the Gram part
+// (sum of wA xs^q, which does not involve the cashflows) and the
+// right-hand side (sum of wB xs^q pvj), with the same product chain, so each
+// sum is bitwise the one moments_add forms.  gram_add stores the Laguerre
+// weight for rhs_add and the exercise update.
 template <int D, bool LAG>
-__device__ __forceinline__ int moments_add2(double *acc, double *acc2, double s0, double pv0, double s1,
-                                            double pv1, double K, bool call, double xa, double xb, double wc,
-                                            double *w0, double *w1)
+__device__ __forceinline__ bool gram_add(double *acc, double s, double sg, double nsk, double xa, double xb,
+                                         double wc, double *wout)
 {
-    constexpr int NA = 2 * D + 1, NB = D + 1;
-    const int c = moments_add<D, LAG, false>(acc, s0, pv0, K, call, xa, xb, wc, w0) +
-                  moments_add<D, LAG, false>(acc2, s1, pv1, K, call, xa, xb, wc, w1);
-#pragma unroll
-    for (int q = 0; q < NA + NB; ++q) {
-        asm volatile("" : "+v"(acc[q]));
-        asm volatile("" : "+v"(acc2[q]));
+    constexpr int NA = 2 * D + 1;
+    const bool itm = payoff_arg(s, sg, nsk) > 0.0;
+    const double xs = fma(s, xa, xb);
+    double w = 1.0;
+    if (LAG) {
+        w = lag_weight(s, wc);
+        *wout = w;
     }
-    return c;
+    double y = itm ? w : 0.0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        acc[q] = LAG ? fma(w, y, acc[q]) : acc[q] + y;
+        if (q + 1 < NA) y *= xs;
+    }
+    return itm;
+}
+
+// w: the path's Laguerre weight (1 for monomials), read for every path (a
+// read under the in-the-money mask would wait on each path in turn).
+template <int D>
+__device__ __forceinline__ void rhs_add(double *acc, double s, double pvj, double sg, double nsk, double xa,
+                                        double xb, double w)
+{
+    constexpr int NB = D + 1;
+    const bool itm = payoff_arg(s, sg, nsk) > 0.0;
+    const double xs = fma(s, xa, xb);
+    double y = itm ? w : 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        acc[q] = fma(pvj, y, acc[q]);
+        if (q + 1 < NB) y *= xs;
+    }
 }
 
 // Exercise update at a date: exercise (cashflow dk h) when in the money and
 // dk h exceeds the fitted continuation; else keep pvj.
 template <typename T, int D, bool LAG>
-__device__ __forceinline__ T exercise_update(T s_t, T pvj, double K, bool call, double xa, double xb, double dk,
+__device__ __forceinline__ T exercise_update(T s_t, T pvj, double sg, double nsk, double xa, double xb, double dk,
                                              const double *gam, double wc, const double *wgiven = nullptr)
 {
     constexpr int P = D + 1;
     const double s = (double)s_t;
-    const double h = call ? s - K : K - s;
+    const double h = payoff_arg(s, sg, nsk);
     const double xs = fma(s, xa, xb);
     double cont = gam[P - 1];
 #pragma unroll
     for (int q = P - 2; q >= 0; --q) cont = fma(cont, xs, gam[q]);
     if (LAG) cont *= wgiven ? *wgiven : lag_weight(s, wc);
     const double ex = dk * h;
-    return (h > 0.0 && ex > cont) ? (T)ex : pvj;
+    // in the money and above the continuation: with dk > 0, ex > 0 exactly
+    // when h > 0 (|h| is at least an ulp of K, far from underflow), so this
+    // is the test h > 0 && ex > cont
+    return ex > fmax(cont, 0.0) ? (T)ex : pvj;
 }
 
 // ---------------------------------------------------------------------------
@@ -189,77 +222,303 @@ __device__ __forceinline__ T exercise_update(T s_t, T pvj, double K, bool call, 
 //   a device-wide fixed-order sum that every group receives (allreduce);
 //   every group solves the same normal equations (bitwise the same
 //   coefficients; group 0 keeps the date record); exercise update.
-// KEEP: path values held in registers across the device-wide sum, next
-// date prefetched before waiting.  Otherwise the date is streamed twice (moments,
-// update) through a ring of PD vector loads in flight per thread.
-// Per-path arithmetic is binary64 for both storage types (see moments_add).
+// Per-path arithmetic is binary64 for both storage types (see SweepShape).
 // Rows are padded to a multiple of every tile size with S = K (rounded away
 // from the money in binary32), so padded paths are never in the money and
 // keep pv = 0: no bounds checks.
 // ---------------------------------------------------------------------------
-template <typename T, int PPT, int D, bool LAG>
-__device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
-                                           uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
-                                           double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
-                                           double *s_w, double *s_wl, DateConst *s_dc, int *s_flag)
-{
-    using SH = SweepShape<T, PPT>;
-    constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
-    constexpr bool KEEP = SH::KEEP;
-    constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
-    constexpr int NV = NA + NB + 1;
-    constexpr int RW = row_words(D);
-    constexpr uint32_t JS = 64 * VW;                 // element stride between a lane's vectors
-
-    const int tid = threadIdx.x;
-    const int64_t ld = a.ld;
-    const double K = a.K;
-    const bool call = a.is_call != 0;
-    const double wc = -0.5 / a.K;   // Laguerre weight exponent per unit S
-    const uint32_t G = (uint32_t)a.G;
-    const int64_t tile0 = (int64_t)gid * kWG * PPT;
-    const uint32_t voff = (e0 - (uint32_t)tile0) * (uint32_t)sizeof(T);   // byte offset in the tile
-    constexpr int32_t kTileBytes = kWG * PPT * (int32_t)sizeof(T);
+template <typename T, int PPT>
+struct TileIO {
+    static constexpr int VW = 16 / sizeof(T);
+    static constexpr uint32_t JS = 64 * VW;   // element stride between a lane's vectors
+    static constexpr int32_t kTileBytes = kWG * PPT * (int32_t)sizeof(T);
+    int64_t tile0;
+    uint32_t voff;                            // this lane's byte offset in the tile
+    __device__ TileIO(uint32_t gid, uint32_t e0)
+        : tile0((int64_t)gid * kWG * PPT), voff((e0 - (uint32_t)((int64_t)gid * kWG * PPT)) * (uint32_t)sizeof(T))
+    {
+    }
     // Buffer loads: tile base in SGPRs, one lane offset, constant per-vector
-    // offsets.  Rows are padded to whole tiles with S = K (never in the money).
-    auto vload = [&](const T *row, int jj) -> Vec<T> {
+    // offsets.  Rows are padded to whole tiles (no bounds checks).
+    __device__ __forceinline__ Vec<T> load(const T *row, int jj) const
+    {
         __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void *)(row + tile0), (short)0, kTileBytes, 0x00020000);
         return __builtin_bit_cast(Vec<T>, __builtin_amdgcn_raw_buffer_load_b128(
                                                 rs, voff, (uint32_t)jj * JS * (uint32_t)sizeof(T), 0));
-    };
+    }
+};
 
-    {
-        const T *row = S + (size_t)(a.M - 1) * ld;
-        const double dM = a.datec[a.M].disc;
-        // streamed through the same ring as the date passes (issuing every
-        // load at once would hold a second copy of pv[] in registers)
-        Vec<T> ring[PD];
+// Discounted terminal cashflows of the thread's paths (date M), streamed
+// through a ring of PD loads (issuing every load at once would hold a second
+// copy of pv[] in registers).
+template <typename T, int PPT>
+__device__ __forceinline__ void sweep_terminal(const SweepArgs &a, const T *__restrict__ S, const TileIO<T, PPT> &io,
+                                               T (&pv)[PPT])
+{
+    using SH = SweepShape<T, PPT>;
+    constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
+    const double K = a.K;
+    const bool call = a.is_call != 0;
+    const T *row = S + (size_t)(a.M - 1) * a.ld;
+    const double dM = a.datec[a.M].disc;
+    Vec<T> ring[PD];
 #pragma unroll
-        for (int q = 0; q < PD; ++q) ring[q] = vload(row, q);
+    for (int q = 0; q < PD; ++q) ring[q] = io.load(row, q);
+#pragma unroll
+    for (int jj = 0; jj < NVEC; ++jj) {
+        const Vec<T> v = ring[jj % PD];
+        if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const double sv = (double)v.v[e];
+            const double h = call ? sv - K : K - sv;
+            pv[jj * VW + e] = h > 0.0 ? (T)(dM * h) : T(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The solve of date k by thread 0 (registers where the kernel has room,
+// else LDS), and group 0's date record: coefficients, flag and count, the
+// moments, and device clock stamps of the date's phases.
+template <int D, bool REGS>
+__device__ __forceinline__ void solve_and_record(const SweepArgs &a, uint32_t gid, int k, const double *s_tot,
+                                                 double *s_beta, double (*s_L)[8], double *s_w,
+                                                 const uint64_t (&stamp)[3])
+{
+    constexpr int NV = 3 * D + 4;
+    const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
+    if constexpr (REGS) {
+        double Lr[8][8], wr[32];
+        solve_date<D>(s_tot, s_beta, Lr, wr);
+    } else {
+        solve_date<D>(s_tot, s_beta, s_L, s_w);
+    }
+    if (gid == 0) {
+        // every group solved the same system; group 0 keeps the record
+        double *rec = a.rec + (size_t)k * kRec;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) rec[q] = s_beta[q];
+        for (int q = 0; q < NV && q < 22; ++q) rec[10 + q] = s_tot[q];
+        rec[kRecTime + 0] = (double)stamp[0];                             // moments summed in the group
+        rec[kRecTime + 1] = (double)c_all;                                // device-wide totals in hand
+        rec[kRecTime + 2] = (double)__builtin_amdgcn_s_memrealtime();     // solved
+        rec[kRecTime + 3] = (double)stamp[1];                             // next date's Gram part summed
+        rec[kRecTime + 4] = (double)stamp[2];                             // date's pass started
+    }
+}
+
+// Register-resident tile (KEEP): the date's path values stay in registers
+// across the device-wide sum.  The Gram part of the next date's moments
+// depends only on that date's path values, so it is formed while this
+// date's sum is in flight (between publishing and gathering); what remains
+// on the critical path is the right-hand side pass (which needs the
+// cashflows after this date's update), the sum, the solve and the update.
+// Path values are double-buffered plus one prefetch; the Laguerre weights
+// of two dates are cached in LDS ([2][path][thread], each thread touching
+// only its own entries).  Date constants come through uniform vector loads
+// issued a date ahead.
+template <typename T, int PPT, int D, bool LAG>
+__device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
+                                           const TileIO<T, PPT> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                           double (*s_red)[32], double (*s_red2)[32], double *s_tot,
+                                           double *s_beta, double *s_wl, int *s_flag)
+{
+    using SH = SweepShape<T, PPT>;
+    constexpr int VW = SH::VW, NVEC = SH::NVEC;
+    constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
+    constexpr int NG = NA + 1, NV = NA + NB + 1;
+    constexpr int RW = row_words(D);
+    const int tid = threadIdx.x;
+    const int64_t ld = a.ld;
+    const int M = a.M;
+    const double sg = a.is_call ? 1.0 : -1.0, nsk = -sg * a.K;
+    const double wc = -0.5 / a.K;   // Laguerre weight exponent per unit S
+    const uint32_t G = (uint32_t)a.G;
+
+    // date constants: (disc, xa) and (xb, pad) of date k, one line per date
+    const __amdgpu_buffer_rsrc_t drs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.datec, (short)0, (M + 1) * (int)sizeof(DateConst), 0x00020000);
+    auto dload = [&](int k, double (&d)[3]) {
+        using V2 = double __attribute__((ext_vector_type(2)));
+        const V2 u = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b128(drs, 0, k * 32, 0));
+        const V2 v = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b128(drs, 0, k * 32 + 16, 0));
+        d[0] = u.x;
+        d[1] = u.y;
+        d[2] = v.x;
+    };
+    auto wbuf = [&](int k) -> double * { return s_wl + (size_t)(k & 1) * PPT * kWG + tid; };
+
+    // Gram part of date k's moments from its path values v, pairs of paths
+    // into two accumulator sets (independent chains), pinned per pair; the
+    // in-the-money count from wave ballots (scalar unit); result (group
+    // total) valid in thread 0
+    auto gram_pass = [&](const Vec<T>(&v)[NVEC], double xa, double xb, double *wl, double (&g)[NG]) {
+        double g2[NA];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) g[q] = g2[q] = 0.0;
+        uint32_t cnt = 0;
 #pragma unroll
         for (int jj = 0; jj < NVEC; ++jj) {
-            const Vec<T> v = ring[jj % PD];
-            if (jj + PD < NVEC) ring[jj % PD] = vload(row, jj + PD);
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                const double sv = (double)v.v[e];
-                const double h = call ? sv - K : K - sv;
-                pv[jj * VW + e] = h > 0.0 ? (T)(dM * h) : T(0);
+            for (int e = 0; e < VW; e += 2) {
+                const int j0 = jj * VW + e;
+                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * kWG);
+                const bool i1 =
+                    gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc, wl + (j0 + 1) * kWG);
+                cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i0)) +
+                       (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i1));
+#pragma unroll
+                for (int q = 0; q < NA; ++q) {
+                    asm volatile("" : "+v"(g[q]));
+                    asm volatile("" : "+v"(g2[q]));
+                }
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
-    }
-
-    Vec<T> sc[KEEP ? NVEC : 1];
-    Vec<T> sn[KEEP ? NVEC : 1];
-    if (!(a.allow_exercise && a.M >= 2)) return;
-    if (KEEP) {
-        const T *row = S + (size_t)(a.M - 2) * ld;
 #pragma unroll
-        for (int jj = 0; jj < NVEC; ++jj) sc[jj] = vload(row, jj);
+        for (int q = 0; q < NA; ++q) g[q] += g2[q];
+        g[NA] = (double)cnt;
+        group_sum<NG, 1>(g, s_red2);
+    };
+
+    if (!(a.allow_exercise && M >= 2)) return;
+
+    Vec<T> sc[NVEC], sn[NVEC], sp[NVEC];
+    double dcp[3];
+    double dcc[3];
+    dload(M - 1, dcc);
+    {
+        const T *row = S + (size_t)(M - 2) * ld;
+#pragma unroll
+        for (int jj = 0; jj < NVEC; ++jj) sc[jj] = io.load(row, jj);
     }
+    // prefetches are unconditional (the date clamped to 1; unused at the
+    // end), so the loads land in the loop-carried registers directly
+    auto prefetch = [&](int kp) {
+        kp = kp >= 1 ? kp : 1;
+        dload(kp, dcp);
+        const T *row = S + (size_t)(kp - 1) * ld;
+#pragma unroll
+        for (int jj = 0; jj < NVEC; ++jj) sp[jj] = io.load(row, jj);
+    };
+    prefetch(M - 2);
+    double xa = uniform_f64(dcc[1]), xb = uniform_f64(dcc[2]), dk = uniform_f64(dcc[0]);
+    double gt[NG];
+    gram_pass(sc, xa, xb, wbuf(M - 1), gt);
+
+    for (int k = M - 1; k >= 1; --k) {
+        uint64_t stamp[3];
+        stamp[2] = __builtin_amdgcn_s_memrealtime();
+        double rs[NB];
+        {
+            double r2[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) rs[q] = r2[q] = 0.0;
+            // every weight read issued before the first pinned sum (memory
+            // reads do not move across the pins)
+            const double *wl = wbuf(k);
+            double wv[PPT];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) wv[j] = LAG ? wl[j * kWG] : 1.0;
+#pragma unroll
+            for (int jj = 0; jj < NVEC; ++jj) {
+#pragma unroll
+                for (int e = 0; e < VW; e += 2) {
+                    const int j0 = jj * VW + e;
+                    rhs_add<D>(rs, (double)sc[jj].v[e], (double)pv[j0], sg, nsk, xa, xb, wv[j0]);
+                    rhs_add<D>(r2, (double)sc[jj].v[e + 1], (double)pv[j0 + 1], sg, nsk, xa, xb, wv[j0 + 1]);
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) {
+                        asm volatile("" : "+v"(rs[q]));
+                        asm volatile("" : "+v"(r2[q]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) rs[q] += r2[q];
+        }
+        group_sum<NB>(rs, s_red);
+        ++epoch;
+        stamp[0] = __builtin_amdgcn_s_memrealtime();
+        double acc[NV];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[q] = gt[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[NA + q] = rs[q];
+        acc[NV - 1] = gt[NA];
+        if (!allreduce_publish<NV, RW>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
+                                       s_flag)) {
+            alive = false;
+            return;
+        }
+
+        // next date's Gram part while this date's sum is in flight, with the
+        // date after next in flight from memory meanwhile
+        double xan = xa, xbn = xb, dkn = dk;
+#pragma unroll
+        for (int jj = 0; jj < NVEC; ++jj) sn[jj] = sp[jj];
+        if (k >= 2) {
+            xan = uniform_f64(dcp[1]);
+            xbn = uniform_f64(dcp[2]);
+            dkn = uniform_f64(dcp[0]);
+        }
+        prefetch(k - 2);
+        if (k >= 2) gram_pass(sn, xan, xbn, wbuf(k - 1), gt);
+        stamp[1] = __builtin_amdgcn_s_memrealtime();
+
+        if (!allreduce_gather<NV, RW>(G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
+            alive = false;
+            return;
+        }
+        if (tid == 0) solve_and_record<D, true>(a, gid, k, s_tot, s_beta, nullptr, nullptr, stamp);
+        __syncthreads();
+
+        if (s_beta[8] != 0.0) {
+            double gam[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) gam[q] = s_beta[q];
+            const double *wl = wbuf(k);
+#pragma unroll
+            for (int jj = 0; jj < NVEC; ++jj) {
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], sg, nsk, xa, xb, dk,
+                                                                 gam, wc, wl + (jj * VW + e) * kWG);
+                __builtin_amdgcn_sched_barrier(0);   // one vector's paths at a time
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NVEC; ++jj) sc[jj] = sn[jj];
+        xa = xan;
+        xb = xbn;
+        dk = dkn;
+        __syncthreads();   // s_beta reuse
+    }
+}
+
+// Streamed tile: the date's slab is read twice (moments, then update)
+// through a ring of PD vector loads in flight per thread; date constants
+// staged in LDS.
+template <typename T, int PPT, int D, bool LAG>
+__device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
+                                             const TileIO<T, PPT> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                             double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
+                                             double *s_w, DateConst *s_dc, int *s_flag)
+{
+    using SH = SweepShape<T, PPT>;
+    constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
+    constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
+    constexpr int NV = NA + NB + 1;
+    constexpr int RW = row_words(D);
+    const int tid = threadIdx.x;
+    const int64_t ld = a.ld;
+    const double sg = a.is_call ? 1.0 : -1.0, nsk = -sg * a.K;
+    const double wc = -0.5 / a.K;
+    const uint32_t G = (uint32_t)a.G;
+
+    if (!(a.allow_exercise && a.M >= 2)) return;
     // date constants staged in LDS (a dependent global load at the top of
     // each date would stall the moment pass)
     for (int k = tid; k <= a.M; k += kWG) s_dc[k] = a.datec[k];
@@ -268,42 +527,25 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         const double xa = uniform_f64(s_dc[k].xa), xb = uniform_f64(s_dc[k].xb),
                      dk = uniform_f64(s_dc[k].disc);
         const T *row = S + (size_t)(k - 1) * ld;
+        uint64_t stamp[3];
+        stamp[2] = __builtin_amdgcn_s_memrealtime();
 
         double acc[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         int cnt = 0;
-        if (KEEP) {
-            // path pairs: two independent chains per step (one wave per SIMD
-            // at a group per CU leaves the binary64 latencies to ILP)
-            double acc2[NV];
-#pragma unroll
-            for (int q = 0; q < NV; ++q) acc2[q] = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < NVEC; ++jj) {
-#pragma unroll
-                for (int e = 0; e < VW; e += 2) {
-                    const int j0 = jj * VW + e;
-                    cnt += moments_add2<D, LAG>(acc, acc2, (double)sc[jj].v[e], (double)pv[j0],
-                                                (double)sc[jj].v[e + 1], (double)pv[j0 + 1], K, call, xa, xb,
-                                                wc, LAG ? &s_wl[j0 * kWG + tid] : nullptr,
-                                                LAG ? &s_wl[(j0 + 1) * kWG + tid] : nullptr);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += acc2[q];
-        } else {
+        {
             Vec<T> ring[PD];
 #pragma unroll
-            for (int q = 0; q < PD; ++q) ring[q] = vload(row, q);
+            for (int q = 0; q < PD; ++q) ring[q] = io.load(row, q);
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
                 const Vec<T> cur = ring[jj % PD];
-                if (jj + PD < NVEC) ring[jj % PD] = vload(row, jj + PD);
+                if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
-                    cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], K, call, xa, xb, wc);
+                    cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], sg, nsk, xa, xb, wc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -314,78 +556,66 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         group_sum<NV>(acc, s_red);
         ++epoch;
         // (a clock read before group_sum would pin the moment pass's schedule)
-        const uint64_t c_sum = __builtin_amdgcn_s_memrealtime();
-
-        if (KEEP && k >= 2) {
-            // next date's values: in flight while the epoch completes
-            const T *nrow = S + (size_t)(k - 2) * ld;
-#pragma unroll
-            for (int jj = 0; jj < NVEC; ++jj) sn[jj] = vload(nrow, jj);
-        }
+        stamp[0] = stamp[1] = __builtin_amdgcn_s_memrealtime();
         if (!allreduce<NV, RW>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
             alive = false;
             return;
         }
-        if (tid == 0) {
-            const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
-            if constexpr (KEEP) {
-                double Lr[8][8], wr[32];
-                solve_date<D>(s_tot, s_beta, Lr, wr);
-            } else {
-                solve_date<D>(s_tot, s_beta, s_L, s_w);
-            }
-            if (gid == 0) {
-                // every group solved the same system; group 0 keeps the record
-                double *rec = a.rec + (size_t)k * kRec;
-#pragma unroll
-                for (int q = 0; q < 10; ++q) rec[q] = s_beta[q];
-                for (int q = 0; q < NV && q < 22; ++q) rec[10 + q] = s_tot[q];
-                rec[kRecTime + 0] = (double)c_sum;                                // moments summed in the group
-                rec[kRecTime + 1] = (double)c_all;                                // device-wide totals in hand
-                rec[kRecTime + 2] = (double)__builtin_amdgcn_s_memrealtime();     // solved
-            }
-        }
+        if (tid == 0) solve_and_record<D, false>(a, gid, k, s_tot, s_beta, s_L, s_w, stamp);
         __syncthreads();
 
         if (s_beta[8] != 0.0) {
             double gam[P];
 #pragma unroll
             for (int q = 0; q < P; ++q) gam[q] = s_beta[q];
-            if (KEEP) {
+            Vec<T> ring[PD];
 #pragma unroll
-                for (int jj = 0; jj < NVEC; ++jj) {
+            for (int q = 0; q < PD; ++q) ring[q] = io.load(row, q);
 #pragma unroll
-                    for (int e = 0; e < VW; ++e)
-                        pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], K, call, xa,
-                                                                     xb, dk, gam, wc,
-                                                                     LAG ? &s_wl[(jj * VW + e) * kWG + tid] : nullptr);
-                    __builtin_amdgcn_sched_barrier(0);   // one vector's paths at a time
-                }
-            } else {
-                Vec<T> ring[PD];
+            for (int jj = 0; jj < NVEC; ++jj) {
+                const Vec<T> cur = ring[jj % PD];
+                if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int q = 0; q < PD; ++q) ring[q] = vload(row, q);
-#pragma unroll
-                for (int jj = 0; jj < NVEC; ++jj) {
-                    const Vec<T> cur = ring[jj % PD];
-                    if (jj + PD < NVEC) ring[jj % PD] = vload(row, jj + PD);
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        pv[jj * VW + e] = exercise_update<T, D, LAG>(cur.v[e], pv[jj * VW + e], K, call, xa, xb,
-                                                                     dk, gam, wc);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
+                for (int e = 0; e < VW; ++e) {
+                    pv[jj * VW + e] = exercise_update<T, D, LAG>(cur.v[e], pv[jj * VW + e], sg, nsk, xa, xb, dk, gam,
+                                                                 wc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        if (KEEP) {
-#pragma unroll
-            for (int jj = 0; jj < NVEC; ++jj) sc[jj] = sn[jj];
         }
         __syncthreads();   // s_beta reuse
     }
+}
+
+// LDS of one sweep workgroup.
+template <typename T, int PPT, bool LAG>
+struct SweepLds {
+    static constexpr bool KEEP = SweepShape<T, PPT>::KEEP;
+    double red[kWaves][32];
+    double red2[kWaves][32];
+    double tot[32];
+    double beta[10];
+    double L[KEEP ? 1 : 8][8];
+    double w[KEEP ? 1 : 32];
+    // Laguerre weights of a KEEP tile, [2 dates][path][thread]
+    double wl[LAG && KEEP ? 2 * PPT * kWG : 1];
+    DateConst dc[KEEP ? 1 : kMaxDates + 1];
+    int flag[2 + kWaves];
+};
+
+template <typename T, int PPT, int D, bool LAG>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
+                                           uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                           SweepLds<T, PPT, LAG> &L)
+{
+    const TileIO<T, PPT> io(gid, e0);
+    sweep_terminal<T, PPT>(a, S, io, pv);
+    if constexpr (SweepShape<T, PPT>::KEEP)
+        sweep_keep<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.flag);
+    else
+        sweep_stream<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc, L.flag);
 }
 
 // Epilogue (eqs. (6)-(8)): FP64 sums of the discounted cashflows and their
@@ -467,47 +697,28 @@ __device__ __forceinline__ uint32_t tile_e0(uint32_t gid)
 }
 
 template <typename T, int PPT, int D, bool LAG>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(SweepShape<T, PPT>::template waves<D, LAG>())))
 sweep_kernel(SweepArgs a, const T *__restrict__ S)
 {
     static_assert(PPT % (16 / sizeof(T)) == 0, "PPT must be a multiple of the vector width");
-    __shared__ double s_red[kWaves][32];
-    __shared__ double s_tot[32];
-    __shared__ double s_beta[10];
-    __shared__ double s_L[8][8];
-    __shared__ double s_w[32];
-    // Laguerre weights of a KEEP tile, [path][thread], between the moment
-    // pass and the exercise update of a date
-    __shared__ double s_wl[LAG && SweepShape<T, PPT>::KEEP ? PPT * kWG : 1];
-    __shared__ DateConst s_dc[kMaxDates + 1];
-    __shared__ int s_flag[1 + kWaves];
+    __shared__ SweepLds<T, PPT, LAG> L;
 
     const uint32_t gid = blockIdx.x;
     const uint32_t e0 = tile_e0<T, PPT>(gid);
     T pv[PPT];
     uint32_t epoch = 0;
     bool alive = true;
-    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w, s_wl, s_dc,
-                               s_flag);
+    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, L);
     if (!alive) return;
-    sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
+    sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
 }
 
 template <typename T, int PPT, int D, bool LAG>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(SweepShape<T, PPT>::template waves<D, LAG>())))
 sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict__ tile_opt,
                    BatchGlobal g)
 {
-    __shared__ double s_red[kWaves][32];
-    __shared__ double s_tot[32];
-    __shared__ double s_beta[10];
-    __shared__ double s_L[8][8];
-    __shared__ double s_w[32];
-    // Laguerre weights of a KEEP tile, [path][thread], between the moment
-    // pass and the exercise update of a date
-    __shared__ double s_wl[LAG && SweepShape<T, PPT>::KEEP ? PPT * kWG : 1];
-    __shared__ DateConst s_dc[kMaxDates + 1];
-    __shared__ int s_flag[1 + kWaves];
+    __shared__ SweepLds<T, PPT, LAG> L;
     __shared__ int s_claim;
 
     for (;;) {
@@ -545,10 +756,9 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
         T pv[PPT];
         uint32_t epoch = 0;
         bool alive = true;
-        sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, s_red, s_tot, s_beta, s_L, s_w,
-                                   s_wl, s_dc, s_flag);
+        sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, L);
         if (!alive) return;
-        sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, s_red, s_tot, s_flag);
+        sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
     }
 }
 

@@ -25,22 +25,24 @@ __device__ __forceinline__ void raise_error(uint32_t *err)
     __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// x + (the value DPP control `CTRL` moves into this lane, in the rows of
-// ROW_MASK; +0 in the other rows).  binary64 through two 32-bit DPP moves.
+// x + (the value DPP control `CTRL` moves into this lane), binary64 through
+// two 32-bit DPP moves.  Lanes outside ROW_MASK, or without a source lane,
+// get an unspecified value: only lane 63 of the final sum is used, and it
+// depends on none of them.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_add(double x)
 {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, ROW_MASK, 0xF, false);
-    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
     return x + __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Sum of x over the 64 lanes of a wave, valid in lane 63, in a fixed order
-// on the vector unit (DPP, no LDS round trips): neighbour swaps within quads,
-// the half-row and row mirrors (every lane of a 16-lane row then holds the
-// row sum), then row 0 into row 1 and row 2 into row 3 (row_bcast:15), and
-// lane 31 into rows 2 and 3 (row_bcast:31).
+// Sum of x over the 64 lanes of a wave, valid in lane 63 (other lanes hold
+// unspecified values), in a fixed order on the vector unit (DPP, no LDS
+// round trips): neighbour swaps within quads, the half-row and row mirrors
+// (every lane of a 16-lane row then holds the row sum), then row 2 into row 3
+// (row_bcast:15) and row 1 into row 3 (row_bcast:31).
 __device__ __forceinline__ double wave_sum(double x)
 {
     x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
@@ -74,13 +76,15 @@ __device__ __forceinline__ double add_halves32(double x)
 }
 
 // Sum NV doubles over the workgroup in a fixed order (wave_sum in each wave,
-// then waves 0..3 in order).  Result valid in thread 0.
-template <int NV>
+// then waves 0..3 in order).  The last NU components are wave-uniform (a
+// wave's total already, e.g. a ballot count): summed over the waves only.
+// Result valid in thread 0.
+template <int NV, int NU = 0>
 __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    for (int q = 0; q < NV - NU; ++q) v[q] = wave_sum(v[q]);
     if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) s_red[wave][q] = v[q];
@@ -158,6 +162,7 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
 // Waits are bounded by `limit` polls; on running out, or on seeing the error
 // word raised by another group, returns false (the caller exits).
 // v: valid in thread 0.  tot: LDS [>= NV], valid in every thread on return.
+// s_flag: LDS [2 + kWaves].
 // ---------------------------------------------------------------------------
 // Fixed-order sum of rows [0, count) of `slots` (RW words each, tagged):
 // lane c of each RW-lane slice reads word c, KB rows per thread in flight;
@@ -238,29 +243,40 @@ __device__ __forceinline__ void put_row(uint64_t *row, const double *v, uint64_t
 // first (see allreduce).
 constexpr uint32_t kFlatMaxGroups = 256;
 
+// Publishing half of allreduce: thread 0 stores the group's row and bumps
+// its team's counter; above kFlatMaxGroups the team's last arriver also sums
+// its team's rows into the team row.  The caller may do independent work
+// before the gathering half (allreduce_gather) with the same epoch.  Uses
+// s_flag[1 + kWaves] (the team-last flag), so that the gathering half's flags
+// never overlap it.
 template <int NV, int RW>
-__device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
-                                 uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
-                                 double (*s_red)[32], int *s_flag)
+__device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
+                                         uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit,
+                                         double *tot, double (*s_red)[32], int *s_flag)
 {
     static_assert(NV <= RW && RW <= 32 && (RW & (RW - 1)) == 0, "row width");
     const uint64_t tag = epoch & 3u;
     uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
     uint64_t *tslots = rows + (size_t)2 * G * RW + (size_t)(epoch & 1u) * kMaxTeams * RW;
-    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
+    const uint32_t TS = team_size(G);
     const uint32_t tau = gid / TS;
     const bool flat = G <= kFlatMaxGroups;
-    if (threadIdx.x == 0) {
-        put_row<NV>(slots + (size_t)gid * RW, v, tag);
-        const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        s_flag[0] = (!flat && old + 1u == epoch * min(TS, G - tau * TS)) ? 1 : 0;   // team's last arrival
-    }
-    if (!flat) {
+    if (threadIdx.x == 0) put_row<NV>(slots + (size_t)gid * RW, v, tag);
+    if (flat) {
+        // the counter's old value is not used: nothing waits for the round trip
+        if (threadIdx.x == 0)
+            (void)__hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
         // team level: the team's last arriver sums its team's rows in member
         // order and publishes the team row (tagged like the group rows)
+        if (threadIdx.x == 0) {
+            const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            s_flag[1 + kWaves] = old + 1u == epoch * min(TS, G - tau * TS) ? 1 : 0;
+        }
         __syncthreads();
-        if (s_flag[0]) {
+        if (s_flag[1 + kWaves]) {
             const uint32_t first = tau * TS;
             if (!sum_rows<NV, RW>(slots + (size_t)first * RW, min(TS, G - first), tag, err, limit, tot, s_red,
                                   s_flag))
@@ -268,6 +284,21 @@ __device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G
             if (threadIdx.x == 0) put_row<NV>(tslots + (size_t)tau * RW, tot, tag);
         }
     }
+    return true;
+}
+
+// Gathering half: wait until every group (or team) of `epoch` has published,
+// then sum the rows in the fixed order into tot (LDS, every thread).
+template <int NV, int RW>
+__device__ inline bool allreduce_gather(uint32_t G, uint64_t *rows, uint32_t *words, uint32_t *err,
+                                        uint32_t epoch, uint32_t limit, double *tot, double (*s_red)[32],
+                                        int *s_flag)
+{
+    const uint64_t tag = epoch & 3u;
+    uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
+    uint64_t *tslots = rows + (size_t)2 * G * RW + (size_t)(epoch & 1u) * kMaxTeams * RW;
+    const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
+    const bool flat = G <= kFlatMaxGroups;
     if (threadIdx.x < 64) {
         // flat: lane t < NT watches team t's counter; teams: lane t watches
         // team t's row (word 0 carries the epoch tag).  Wave-uniform exit.
@@ -296,6 +327,15 @@ __device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G
     __syncthreads();
     if (!s_flag[0]) return false;
     return sum_rows<NV, RW>(flat ? slots : tslots, flat ? G : NT, tag, err, limit, tot, s_red, s_flag);
+}
+
+template <int NV, int RW>
+__device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
+                                 uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
+                                 double (*s_red)[32], int *s_flag)
+{
+    return allreduce_publish<NV, RW>(v, gid, G, rows, words, err, epoch, limit, tot, s_red, s_flag) &&
+           allreduce_gather<NV, RW>(G, rows, words, err, epoch, limit, tot, s_red, s_flag);
 }
 
 }  // namespace amq
