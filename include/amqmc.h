@@ -295,6 +295,12 @@ int am_server_destroy(am_server *server);
  * order (differences at rounding level). */
 void am_debug_set_batch_ppt(int32_t ppt);
 
+/* Tuning hook: allow (1, the default) or forbid (0) 512-thread workgroups in
+ * single-option sweeps on this thread.  The tile size chosen for a given
+ * n_paths may differ, which changes the reduction order (differences at
+ * rounding level). */
+void am_debug_set_sweep_wide(int32_t allow);
+
 /* Test hook: bound the device-side barrier waits of subsequent calls on this
  * thread to `spins` polls (0 restores the default).  A wait that runs out
  * makes the call return AM_ETIMEOUT after every workgroup has exited. */

@@ -142,6 +142,8 @@ def lib():
         L.am_batch_graph_destroy.restype = ctypes.c_int
         L.am_debug_set_batch_ppt.argtypes = [i32]
         L.am_debug_set_batch_ppt.restype = None
+        L.am_debug_set_sweep_wide.argtypes = [i32]
+        L.am_debug_set_sweep_wide.restype = None
         L.am_last_error.argtypes = []
         L.am_last_error.restype = ctypes.c_char_p
         L.am_max_dates.argtypes = []
@@ -374,6 +376,10 @@ class Server:
 
 def am_debug_set_batch_ppt(ppt: int) -> None:
     lib().am_debug_set_batch_ppt(int(ppt))
+
+
+def am_debug_set_sweep_wide(allow: bool) -> None:
+    lib().am_debug_set_sweep_wide(1 if allow else 0)
 
 
 def am_last_error() -> str:

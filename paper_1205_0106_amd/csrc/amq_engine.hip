@@ -141,7 +141,7 @@ int max_slot(const std::vector<amq::BridgeNode> &s)
     return mx;
 }
 
-struct Plan { int ppt; int G; };
+struct Plan { int wg; int ppt; int G; };
 
 struct DevState {
     int dev = -1;
@@ -154,7 +154,7 @@ struct DevState {
     hipStream_t stream = nullptr;                   // synchronous entry point
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    std::map<long, int> occ;                        // (fp64, ppt, degree) -> groups per CU
+    std::map<long, int> occ;                        // (kind, fp64, wg, ppt, degree) -> groups per CU
 };
 
 std::mutex g_dev_mu;
@@ -201,19 +201,26 @@ int get_schedule(DevState *st, int M, const amq::BridgeNode **out)
     return AM_OK;
 }
 
-int groups_per_cu(DevState *st, int fp64, int laguerre, int ppt, int degree)
+int groups_per_cu(DevState *st, int fp64, int laguerre, int wg, int ppt, int degree)
 {
-    const long key = ((long)laguerre << 24) | ((long)fp64 << 20) | ((long)ppt << 4) | degree;
+    const long key = ((long)(wg == 512) << 28) | ((long)laguerre << 24) | ((long)fp64 << 20) | ((long)ppt << 4) |
+                     degree;
     std::lock_guard<std::mutex> lk(st->mu);
     auto it = st->occ.find(key);
     if (it != st->occ.end()) return it->second;
-    const int nb = amq::sweep_blocks_per_cu(fp64, laguerre, ppt, degree);
+    const int nb = amq::sweep_blocks_per_cu(fp64, laguerre, wg, ppt, degree);
     st->occ[key] = nb;
     return nb;
 }
 
-const int kPPT32[] = {4, 16, 64, 128};
-const int kPPT64[] = {2, 8, 16, 64};
+// Single-option tiles (threads per group, paths per thread).  The 512-thread
+// forms of the register-resident tiles come first, so they win ties with the
+// 256-thread form of the same tile size.
+struct TileShape { int wg, ppt; };
+const TileShape kTiles32[] = {{512, 4}, {256, 4}, {512, 8}, {256, 16}, {256, 64}, {256, 128}};
+const TileShape kTiles64[] = {{512, 2}, {256, 2}, {512, 4}, {256, 8}, {256, 16}, {256, 64}};
+const int kNTiles = 6;
+thread_local int32_t g_sweep_wide = 1;   // 0: single-option sweeps use 256-thread groups only
 
 // Tile choice for one sweep.  Every date costs one device-wide sum, whose
 // latency grows with the group count G (every group reads every group's
@@ -222,24 +229,25 @@ const int kPPT64[] = {2, 8, 16, 64};
 // co-resident, take the one with the least modelled time per date.
 int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Plan *p)
 {
-    const int *ppts = fp64 ? kPPT64 : kPPT32;
-    const int n = 4;
+    const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
     double best = 0.0;
     bool found = false;
-    for (int i = 0; i < n; ++i) {
-        const int ppt = ppts[i];
-        const int per_cu = groups_per_cu(st, fp64, laguerre, ppt, degree);
+    for (int i = 0; i < kNTiles; ++i) {
+        const int wg = tiles[i].wg, ppt = tiles[i].ppt;
+        if (wg != amq::kWG && !g_sweep_wide) continue;
+        const int per_cu = groups_per_cu(st, fp64, laguerre, wg, ppt, degree);
         if (per_cu <= 0) continue;
         int64_t gmax = (int64_t)per_cu * st->num_cu;
         if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
-        const int64_t G = (N + (int64_t)amq::kWG * ppt - 1) / ((int64_t)amq::kWG * ppt);
+        const int64_t tile = (int64_t)wg * ppt;
+        const int64_t G = (N + tile - 1) / tile;
         if (G > gmax) continue;
         // per-date work: ~40 lane operations per path (binary64: ~2x) at
         // 64 lanes x 4 SIMDs x 2.4 GHz per CU, on the CUs the grid covers
         const double cus = (double)(G < st->num_cu ? G : st->num_cu);
         const double work_us = (double)N * (fp64 ? 80.0 : 40.0) / (cus * 4.0 * 16.0 * 2.4e3);
         const double t = 4.5 + 0.013 * (double)G + work_us;
-        if (!found || t < best) { best = t; p->ppt = ppt; p->G = (int)G; found = true; }
+        if (!found || t < best) { best = t; p->wg = wg; p->ppt = ppt; p->G = (int)G; found = true; }
     }
     if (found) return AM_OK;
     return fail(AM_EDIM, "n_paths = %lld exceeds what one resident sweep holds on this device",
@@ -351,9 +359,9 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     sa.rep_out = rep >= 0 ? (double *)(ws + L.off_rep) : nullptr;
     sa.rep = rep;
     sa.n_rep = n_rep;
-    hipError_t e = amq::launch_sweep(sa, fp64, plan.ppt, stream);
+    hipError_t e = amq::launch_sweep(sa, fp64, plan.wg, plan.ppt, stream);
     if (e != hipSuccess)
-        return fail(AM_EDEVICE, "sweep launch (ppt %d, groups %d) failed: %s", plan.ppt, plan.G,
+        return fail(AM_EDEVICE, "sweep launch (%d threads, ppt %d, groups %d) failed: %s", plan.wg, plan.ppt, plan.G,
                     hipGetErrorString(e));
     if (pr) HIP_TRY(hipEventRecord(pr->e[2], stream));
     return AM_OK;
@@ -396,15 +404,14 @@ int64_t am_max_paths(int32_t dtype)
     DevState *st = nullptr;
     if (get_state(&st)) return 0;
     const int fp64 = dtype == AM_FP64;
-    const int *ppts = fp64 ? kPPT64 : kPPT32;
-    const int n = 4;
+    const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
     int64_t best = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < kNTiles; ++i) {
         int64_t worst = -1;
         for (int d = 0; d < 2 * (AM_MAX_DEGREE + 1); ++d) {
-            int64_t g = (int64_t)groups_per_cu(st, fp64, d & 1, ppts[i], d >> 1) * st->num_cu;
+            int64_t g = (int64_t)groups_per_cu(st, fp64, d & 1, tiles[i].wg, tiles[i].ppt, d >> 1) * st->num_cu;
             if (g > amq::kMaxGroups) g = amq::kMaxGroups;
-            const int64_t cap = g * amq::kWG * ppts[i];
+            const int64_t cap = g * tiles[i].wg * tiles[i].ppt;
             worst = worst < 0 || cap < worst ? cap : worst;
         }
         best = worst > best ? worst : best;
@@ -822,6 +829,8 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
 }
 
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
+
+void am_debug_set_sweep_wide(int32_t allow) { g_sweep_wide = allow ? 1 : 0; }
 
 int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
                       void *d_workspace, size_t ws_bytes, void *hip_stream, int32_t *best_ppt,

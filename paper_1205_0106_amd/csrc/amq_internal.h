@@ -141,11 +141,12 @@ struct BatchGlobal {
 
 // Launchers (defined with the kernels).
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s);
-// Returns hipErrorInvalidValue if no kernel exists for (fp64, a.laguerre,
-// ppt, a.degree).
-hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s);
+// Single-option sweep with wg (256 or 512) threads per group.  Returns
+// hipErrorInvalidValue if no kernel exists for (fp64, a.laguerre, wg, ppt,
+// a.degree).
+hipError_t launch_sweep(const SweepArgs &a, int fp64, int wg, int ppt, hipStream_t s);
 // Workgroups of the sweep kernel that fit on one CU (0: no such kernel).
-int sweep_blocks_per_cu(int fp64, int laguerre, int ppt, int degree);
+int sweep_blocks_per_cu(int fp64, int laguerre, int wg, int ppt, int degree);
 size_t generate_lds_bytes(int M);
 hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
@@ -155,10 +156,11 @@ hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, con
                               int grid, int fp64, int ppt, int degree, bool cooperative, hipStream_t s);
 int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree);
 // Sweep kernel tables, one translation unit per (precision, basis kind);
-// batch != 0 selects the many-option kernel.  Null where not built.
-const void *sweep_table_f32_mono(int ppt, int degree, int batch);
-const void *sweep_table_f32_lag(int ppt, int degree, int batch);
-const void *sweep_table_f64_mono(int ppt, int degree, int batch);
-const void *sweep_table_f64_lag(int ppt, int degree, int batch);
+// kind 0: single option, 256-thread groups; 1: many options; 2: single
+// option, 512-thread groups.  Null where not built.
+const void *sweep_table_f32_mono(int ppt, int degree, int kind);
+const void *sweep_table_f32_lag(int ppt, int degree, int kind);
+const void *sweep_table_f64_mono(int ppt, int degree, int kind);
+const void *sweep_table_f64_lag(int ppt, int degree, int kind);
 
 }  // namespace amq

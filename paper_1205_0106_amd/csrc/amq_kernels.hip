@@ -374,28 +374,29 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Dispatch over (precision, basis kind, paths per thread, degree).
 // ---------------------------------------------------------------------------
-static const void *sweep_lookup(int fp64, int laguerre, int ppt, int degree, int batch)
+static const void *sweep_lookup(int fp64, int laguerre, int ppt, int degree, int kind)
 {
-    if (fp64) return laguerre ? sweep_table_f64_lag(ppt, degree, batch) : sweep_table_f64_mono(ppt, degree, batch);
-    return laguerre ? sweep_table_f32_lag(ppt, degree, batch) : sweep_table_f32_mono(ppt, degree, batch);
+    if (fp64) return laguerre ? sweep_table_f64_lag(ppt, degree, kind) : sweep_table_f64_mono(ppt, degree, kind);
+    return laguerre ? sweep_table_f32_lag(ppt, degree, kind) : sweep_table_f32_mono(ppt, degree, kind);
 }
 
-static int blocks_per_cu(const void *f)
+static int blocks_per_cu(const void *f, int wg)
 {
     if (!f) return 0;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWG, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, wg, 0) != hipSuccess) return 0;
     return nb;
 }
 
-int sweep_blocks_per_cu(int fp64, int laguerre, int ppt, int degree)
+int sweep_blocks_per_cu(int fp64, int laguerre, int wg, int ppt, int degree)
 {
-    return blocks_per_cu(sweep_lookup(fp64, laguerre, ppt, degree, 0));
+    if (wg != kWG && wg != 512) return 0;
+    return blocks_per_cu(sweep_lookup(fp64, laguerre, ppt, degree, wg == 512 ? 2 : 0), wg);
 }
 
 int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree)
 {
-    return blocks_per_cu(sweep_lookup(fp64, laguerre, ppt, degree, 1));
+    return blocks_per_cu(sweep_lookup(fp64, laguerre, ppt, degree, 1), kWG);
 }
 
 // Dynamic LDS that leaves room for one workgroup of `f` per CU (more than
@@ -416,9 +417,10 @@ static size_t one_per_cu_lds(const void *f)
     return dyn;
 }
 
-hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs &a, int fp64, int wg, int ppt, hipStream_t s)
 {
-    const void *f = sweep_lookup(fp64, a.laguerre, ppt, a.degree, 0);
+    if (wg != kWG && wg != 512) return hipErrorInvalidValue;
+    const void *f = sweep_lookup(fp64, a.laguerre, ppt, a.degree, wg == 512 ? 2 : 0);
     if (!f) return hipErrorInvalidValue;
     SweepArgs args = a;
     const void *Sp = a.S;
@@ -428,7 +430,7 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int ppt, hipStream_t s)
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && a.G <= cus)
         dyn = one_per_cu_lds(f);
-    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3(kWG), params, (unsigned)dyn, s);
+    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3((unsigned)wg), params, (unsigned)dyn, s);
 }
 
 // ---------------------------------------------------------------------------

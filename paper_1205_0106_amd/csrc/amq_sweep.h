@@ -227,15 +227,15 @@ __device__ __forceinline__ T exercise_update(T s_t, T pvj, double sg, double nsk
 // from the money in binary32), so padded paths are never in the money and
 // keep pv = 0: no bounds checks.
 // ---------------------------------------------------------------------------
-template <typename T, int PPT>
+template <typename T, int PPT, int WG>
 struct TileIO {
     static constexpr int VW = 16 / sizeof(T);
     static constexpr uint32_t JS = 64 * VW;   // element stride between a lane's vectors
-    static constexpr int32_t kTileBytes = kWG * PPT * (int32_t)sizeof(T);
+    static constexpr int32_t kTileBytes = WG * PPT * (int32_t)sizeof(T);
     int64_t tile0;
     uint32_t voff;                            // this lane's byte offset in the tile
     __device__ TileIO(uint32_t gid, uint32_t e0)
-        : tile0((int64_t)gid * kWG * PPT), voff((e0 - (uint32_t)((int64_t)gid * kWG * PPT)) * (uint32_t)sizeof(T))
+        : tile0((int64_t)gid * WG * PPT), voff((e0 - (uint32_t)((int64_t)gid * WG * PPT)) * (uint32_t)sizeof(T))
     {
     }
     // Buffer loads: tile base in SGPRs, one lane offset, constant per-vector
@@ -252,8 +252,8 @@ struct TileIO {
 // Discounted terminal cashflows of the thread's paths (date M), streamed
 // through a ring of PD loads (issuing every load at once would hold a second
 // copy of pv[] in registers).
-template <typename T, int PPT>
-__device__ __forceinline__ void sweep_terminal(const SweepArgs &a, const T *__restrict__ S, const TileIO<T, PPT> &io,
+template <typename T, int PPT, int WG>
+__device__ __forceinline__ void sweep_terminal(const SweepArgs &a, const T *__restrict__ S, const TileIO<T, PPT, WG> &io,
                                                T (&pv)[PPT])
 {
     using SH = SweepShape<T, PPT>;
@@ -320,9 +320,9 @@ __device__ __forceinline__ void solve_and_record(const SweepArgs &a, uint32_t gi
 // of two dates are cached in LDS ([2][path][thread], each thread touching
 // only its own entries).  Date constants come through uniform vector loads
 // issued a date ahead.
-template <typename T, int PPT, int D, bool LAG>
+template <typename T, int PPT, int D, bool LAG, int WG>
 __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
-                                           const TileIO<T, PPT> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                           const TileIO<T, PPT, WG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                            double (*s_red)[32], double (*s_red2)[32], double *s_tot,
                                            double *s_beta, double *s_wl, int *s_flag)
 {
@@ -349,7 +349,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
         d[1] = u.y;
         d[2] = v.x;
     };
-    auto wbuf = [&](int k) -> double * { return s_wl + (size_t)(k & 1) * PPT * kWG + tid; };
+    auto wbuf = [&](int k) -> double * { return s_wl + (size_t)(k & 1) * PPT * WG + tid; };
 
     // Gram part of date k's moments from its path values v, pairs of paths
     // into two accumulator sets (independent chains), pinned per pair; the
@@ -365,9 +365,9 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int e = 0; e < VW; e += 2) {
                 const int j0 = jj * VW + e;
-                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * kWG);
+                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * WG);
                 const bool i1 =
-                    gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc, wl + (j0 + 1) * kWG);
+                    gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc, wl + (j0 + 1) * WG);
                 cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i0)) +
                        (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i1));
 #pragma unroll
@@ -380,7 +380,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
         for (int q = 0; q < NA; ++q) g[q] += g2[q];
         g[NA] = (double)cnt;
-        group_sum<NG, 1>(g, s_red2);
+        group_sum<NG, 1, WG>(g, s_red2);
     };
 
     if (!(a.allow_exercise && M >= 2)) return;
@@ -421,7 +421,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
             const double *wl = wbuf(k);
             double wv[PPT];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) wv[j] = LAG ? wl[j * kWG] : 1.0;
+            for (int j = 0; j < PPT; ++j) wv[j] = LAG ? wl[j * WG] : 1.0;
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
@@ -439,7 +439,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int q = 0; q < NB; ++q) rs[q] += r2[q];
         }
-        group_sum<NB>(rs, s_red);
+        group_sum<NB, 0, WG>(rs, s_red);
         ++epoch;
         stamp[0] = __builtin_amdgcn_s_memrealtime();
         double acc[NV];
@@ -448,7 +448,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[NA + q] = rs[q];
         acc[NV - 1] = gt[NA];
-        if (!allreduce_publish<NV, RW>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
+        if (!allreduce_publish<NV, RW, WG>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
                                        s_flag)) {
             alive = false;
             return;
@@ -468,7 +468,8 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
         if (k >= 2) gram_pass(sn, xan, xbn, wbuf(k - 1), gt);
         stamp[1] = __builtin_amdgcn_s_memrealtime();
 
-        if (!allreduce_gather<NV, RW>(G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
+        if (!allreduce_gather<NV, RW, WG>(G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag,
+                                          k >= 2)) {
             alive = false;
             return;
         }
@@ -485,7 +486,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
                 for (int e = 0; e < VW; ++e)
                     pv[jj * VW + e] = exercise_update<T, D, LAG>(sc[jj].v[e], pv[jj * VW + e], sg, nsk, xa, xb, dk,
-                                                                 gam, wc, wl + (jj * VW + e) * kWG);
+                                                                 gam, wc, wl + (jj * VW + e) * WG);
                 __builtin_amdgcn_sched_barrier(0);   // one vector's paths at a time
             }
         }
@@ -503,7 +504,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 // staged in LDS.
 template <typename T, int PPT, int D, bool LAG>
 __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
-                                             const TileIO<T, PPT> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                             const TileIO<T, PPT, kWG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                              double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
                                              double *s_w, DateConst *s_dc, int *s_flag)
 {
@@ -590,37 +591,39 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
 }
 
 // LDS of one sweep workgroup.
-template <typename T, int PPT, bool LAG>
+template <typename T, int PPT, bool LAG, int WG>
 struct SweepLds {
     static constexpr bool KEEP = SweepShape<T, PPT>::KEEP;
-    double red[kWaves][32];
-    double red2[kWaves][32];
+    double red[WG / 64][32];
+    double red2[WG / 64][32];
     double tot[32];
     double beta[10];
     double L[KEEP ? 1 : 8][8];
     double w[KEEP ? 1 : 32];
     // Laguerre weights of a KEEP tile, [2 dates][path][thread]
-    double wl[LAG && KEEP ? 2 * PPT * kWG : 1];
+    double wl[LAG && KEEP ? 2 * PPT * WG : 1];
     DateConst dc[KEEP ? 1 : kMaxDates + 1];
-    int flag[2 + kWaves];
+    int flag[2 + WG / 64];
 };
 
-template <typename T, int PPT, int D, bool LAG>
+template <typename T, int PPT, int D, bool LAG, int WG>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                            uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
-                                           SweepLds<T, PPT, LAG> &L)
+                                           SweepLds<T, PPT, LAG, WG> &L)
 {
-    const TileIO<T, PPT> io(gid, e0);
-    sweep_terminal<T, PPT>(a, S, io, pv);
-    if constexpr (SweepShape<T, PPT>::KEEP)
-        sweep_keep<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.flag);
-    else
+    const TileIO<T, PPT, WG> io(gid, e0);
+    sweep_terminal<T, PPT, WG>(a, S, io, pv);
+    if constexpr (SweepShape<T, PPT>::KEEP) {
+        sweep_keep<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.flag);
+    } else {
+        static_assert(WG == kWG, "streamed tiles run 256-thread groups");
         sweep_stream<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc, L.flag);
+    }
 }
 
 // Epilogue (eqs. (6)-(8)): FP64 sums of the discounted cashflows and their
 // squares through one more device-wide sum; group 0 writes the result.
-template <typename T, int PPT, int D>
+template <typename T, int PPT, int D, int WG>
 __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, uint32_t e0,
                                             const T (&pv)[PPT], uint32_t epoch, double (*s_red)[32],
                                             double *s_tot, int *s_flag)
@@ -643,10 +646,10 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
         }
         *reinterpret_cast<Vec<T> *>(pvo + e0 + (uint32_t)jj * JS) = o;
     }
-    group_sum<2>(fin, s_red);
+    group_sum<2, 0, WG>(fin, s_red);
     ++epoch;
     const uint32_t G = (uint32_t)a.G;
-    if (!allreduce<2, row_words(D)>(fin, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
+    if (!allreduce<2, row_words(D), WG>(fin, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red,
                                     s_flag))
         return;
     if (gid == 0) {
@@ -688,29 +691,33 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
     }
 }
 
-template <typename T, int PPT>
+template <typename T, int PPT, int WG>
 __device__ __forceinline__ uint32_t tile_e0(uint32_t gid)
 {
     constexpr int VW = 16 / sizeof(T);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    return (uint32_t)((int64_t)gid * kWG * PPT + (int64_t)wave * 64 * PPT + lane * VW);
+    return (uint32_t)((int64_t)gid * WG * PPT + (int64_t)wave * 64 * PPT + lane * VW);
 }
 
-template <typename T, int PPT, int D, bool LAG>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(SweepShape<T, PPT>::template waves<D, LAG>())))
+// WG: threads per group, 256 or (register-resident tiles) 512: two waves
+// of one group per SIMD, so one wave's dependent binary64 latencies and
+// scalar/LDS issue slots overlap the other's vector work.
+template <typename T, int PPT, int D, bool LAG, int WG>
+__global__ void __launch_bounds__(WG)
+__attribute__((amdgpu_waves_per_eu(WG == 512 ? 2 : SweepShape<T, PPT>::template waves<D, LAG>())))
 sweep_kernel(SweepArgs a, const T *__restrict__ S)
 {
     static_assert(PPT % (16 / sizeof(T)) == 0, "PPT must be a multiple of the vector width");
-    __shared__ SweepLds<T, PPT, LAG> L;
+    __shared__ SweepLds<T, PPT, LAG, WG> L;
 
     const uint32_t gid = blockIdx.x;
-    const uint32_t e0 = tile_e0<T, PPT>(gid);
+    const uint32_t e0 = tile_e0<T, PPT, WG>(gid);
     T pv[PPT];
     uint32_t epoch = 0;
     bool alive = true;
-    sweep_body<T, PPT, D, LAG>(a, S, gid, e0, pv, epoch, alive, L);
+    sweep_body<T, PPT, D, LAG, WG>(a, S, gid, e0, pv, epoch, alive, L);
     if (!alive) return;
-    sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
+    sweep_final<T, PPT, D, WG>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
 }
 
 template <typename T, int PPT, int D, bool LAG>
@@ -718,7 +725,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(SweepS
 sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict__ tile_opt,
                    BatchGlobal g)
 {
-    __shared__ SweepLds<T, PPT, LAG> L;
+    __shared__ SweepLds<T, PPT, LAG, kWG> L;
     __shared__ int s_claim;
 
     for (;;) {
@@ -752,76 +759,93 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
         a.pad = 0;
         a.rep_out = nullptr; a.rep = 0; a.n_rep = 0;
         const uint32_t gid = (uint32_t)(t - o.tile_base);
-        const uint32_t e0 = tile_e0<T, PPT>(gid);
+        const uint32_t e0 = tile_e0<T, PPT, kWG>(gid);
         T pv[PPT];
         uint32_t epoch = 0;
         bool alive = true;
-        sweep_body<T, PPT, D, LAG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, L);
+        sweep_body<T, PPT, D, LAG, kWG>(a, (const T *)o.S, gid, e0, pv, epoch, alive, L);
         if (!alive) return;
-        sweep_final<T, PPT, D>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
+        sweep_final<T, PPT, D, kWG>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Kernel addresses by (paths per thread, degree) for one precision and basis
-// kind; `batch` selects the many-option kernel.  Null where not built.  Each
-// (precision, basis kind) pair is instantiated in its own translation unit.
+// kind; `kind` selects the single-option kernel with 256-thread groups (0),
+// the many-option kernel (1) or the single-option kernel with 512-thread
+// groups (2).  Null where not built.  Each (precision, basis kind) pair is
+// instantiated in its own translation unit.
 // ---------------------------------------------------------------------------
-template <typename T, int PPT, int D, bool LAG, bool BATCH>
+template <typename T, int PPT, int D, bool LAG, int KIND>
 inline const void *sweep_addr()
 {
-    if constexpr (BATCH) return (const void *)&sweep_batch_kernel<T, PPT, D, LAG>;
-    else return (const void *)&sweep_kernel<T, PPT, D, LAG>;
+    if constexpr (KIND == 1) return (const void *)&sweep_batch_kernel<T, PPT, D, LAG>;
+    else return (const void *)&sweep_kernel<T, PPT, D, LAG, KIND == 2 ? 512 : kWG>;
 }
 
-template <typename T, int PPT, bool LAG, bool BATCH>
+template <typename T, int PPT, bool LAG, int KIND>
 inline const void *sweep_entry(int degree)
 {
     switch (degree) {
-    case 0: return sweep_addr<T, PPT, 0, LAG, BATCH>();
-    case 1: return sweep_addr<T, PPT, 1, LAG, BATCH>();
-    case 2: return sweep_addr<T, PPT, 2, LAG, BATCH>();
-    case 3: return sweep_addr<T, PPT, 3, LAG, BATCH>();
-    case 4: return sweep_addr<T, PPT, 4, LAG, BATCH>();
-    case 5: return sweep_addr<T, PPT, 5, LAG, BATCH>();
-    case 6: return sweep_addr<T, PPT, 6, LAG, BATCH>();
+    case 0: return sweep_addr<T, PPT, 0, LAG, KIND>();
+    case 1: return sweep_addr<T, PPT, 1, LAG, KIND>();
+    case 2: return sweep_addr<T, PPT, 2, LAG, KIND>();
+    case 3: return sweep_addr<T, PPT, 3, LAG, KIND>();
+    case 4: return sweep_addr<T, PPT, 4, LAG, KIND>();
+    case 5: return sweep_addr<T, PPT, 5, LAG, KIND>();
+    case 6: return sweep_addr<T, PPT, 6, LAG, KIND>();
     default: return nullptr;
     }
 }
 
-// Paths per thread built: binary32 4, 16, 64, 128 (batch 4, 16); binary64
-// 2, 8, 16, 64 (batch 2, 8).
+// Paths per thread built.  binary32: 4, 16, 64, 128 (256-thread groups),
+// 4, 8 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4
+// (512), batch 2, 8.
 template <typename T, bool LAG>
-inline const void *sweep_table(int ppt, int degree, int batch)
+inline const void *sweep_table(int ppt, int degree, int kind)
 {
     if constexpr (sizeof(T) == 8) {
-        if (batch) {
+        if (kind == 1) {
             switch (ppt) {
-            case 2: return sweep_entry<T, 2, LAG, true>(degree);
-            case 8: return sweep_entry<T, 8, LAG, true>(degree);
+            case 2: return sweep_entry<T, 2, LAG, 1>(degree);
+            case 8: return sweep_entry<T, 8, LAG, 1>(degree);
+            default: return nullptr;
+            }
+        }
+        if (kind == 2) {
+            switch (ppt) {
+            case 2: return sweep_entry<T, 2, LAG, 2>(degree);
+            case 4: return sweep_entry<T, 4, LAG, 2>(degree);
             default: return nullptr;
             }
         }
         switch (ppt) {
-        case 2: return sweep_entry<T, 2, LAG, false>(degree);
-        case 8: return sweep_entry<T, 8, LAG, false>(degree);
-        case 16: return sweep_entry<T, 16, LAG, false>(degree);
-        case 64: return sweep_entry<T, 64, LAG, false>(degree);
+        case 2: return sweep_entry<T, 2, LAG, 0>(degree);
+        case 8: return sweep_entry<T, 8, LAG, 0>(degree);
+        case 16: return sweep_entry<T, 16, LAG, 0>(degree);
+        case 64: return sweep_entry<T, 64, LAG, 0>(degree);
         default: return nullptr;
         }
     } else {
-        if (batch) {
+        if (kind == 1) {
             switch (ppt) {
-            case 4: return sweep_entry<T, 4, LAG, true>(degree);
-            case 16: return sweep_entry<T, 16, LAG, true>(degree);
+            case 4: return sweep_entry<T, 4, LAG, 1>(degree);
+            case 16: return sweep_entry<T, 16, LAG, 1>(degree);
+            default: return nullptr;
+            }
+        }
+        if (kind == 2) {
+            switch (ppt) {
+            case 4: return sweep_entry<T, 4, LAG, 2>(degree);
+            case 8: return sweep_entry<T, 8, LAG, 2>(degree);
             default: return nullptr;
             }
         }
         switch (ppt) {
-        case 4: return sweep_entry<T, 4, LAG, false>(degree);
-        case 16: return sweep_entry<T, 16, LAG, false>(degree);
-        case 64: return sweep_entry<T, 64, LAG, false>(degree);
-        case 128: return sweep_entry<T, 128, LAG, false>(degree);
+        case 4: return sweep_entry<T, 4, LAG, 0>(degree);
+        case 16: return sweep_entry<T, 16, LAG, 0>(degree);
+        case 64: return sweep_entry<T, 64, LAG, 0>(degree);
+        case 128: return sweep_entry<T, 128, LAG, 0>(degree);
         default: return nullptr;
         }
     }

@@ -3,9 +3,9 @@
 
 namespace amq {
 
-const void *sweep_table_f64_lag(int ppt, int degree, int batch)
+const void *sweep_table_f64_lag(int ppt, int degree, int kind)
 {
-    return sweep_table<double, true>(ppt, degree, batch);
+    return sweep_table<double, true>(ppt, degree, kind);
 }
 
 }  // namespace amq

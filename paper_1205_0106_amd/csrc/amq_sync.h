@@ -75,11 +75,11 @@ __device__ __forceinline__ double add_halves32(double x)
            __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
 }
 
-// Sum NV doubles over the workgroup in a fixed order (wave_sum in each wave,
-// then waves 0..3 in order).  The last NU components are wave-uniform (a
-// wave's total already, e.g. a ballot count): summed over the waves only.
-// Result valid in thread 0.
-template <int NV, int NU = 0>
+// Sum NV doubles over a workgroup of WG threads in a fixed order (wave_sum
+// in each wave, then the waves in order).  The last NU components are
+// wave-uniform (a wave's total already, e.g. a ballot count): summed over the
+// waves only.  s_red: LDS [WG / 64][32].  Result valid in thread 0.
+template <int NV, int NU = 0, int WG = kWG>
 __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -92,7 +92,12 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = ((s_red[0][q] + s_red[1][q]) + s_red[2][q]) + s_red[3][q];
+        for (int q = 0; q < NV; ++q) {
+            double t = s_red[0][q];
+#pragma unroll
+            for (int w = 1; w < WG / 64; ++w) t += s_red[w][q];
+            v[q] = t;
+        }
     }
 }
 
@@ -162,19 +167,22 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
 // Waits are bounded by `limit` polls; on running out, or on seeing the error
 // word raised by another group, returns false (the caller exits).
 // v: valid in thread 0.  tot: LDS [>= NV], valid in every thread on return.
-// s_flag: LDS [2 + kWaves].
+// s_flag: LDS [2 + WG / 64]; s_red: LDS [WG / 64][32].
 // ---------------------------------------------------------------------------
 // Fixed-order sum of rows [0, count) of `slots` (RW words each, tagged):
 // lane c of each RW-lane slice reads word c, KB rows per thread in flight;
-// every word must carry `tag`, else the rows are read again (bounded).  Each
-// thread adds its rows in ascending order, then the group's lanes and waves
-// in a fixed tree.  tot: LDS [>= NV], valid in every thread on true.
-template <int NV, int RW>
+// every word must carry `tag`, else on_miss(attempt) is called by every
+// thread (a collective wait that returns false to give up) and the rows are
+// read again, at most `limit` times.  Each thread adds its rows in ascending
+// order, then the group's lanes and waves in a fixed tree.  tot: LDS
+// [>= NV], valid in every thread on true.
+template <int NV, int RW, int WG, typename OnMiss>
 __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t tag, uint32_t *err,
-                                uint32_t limit, double *tot, double (*s_red)[32], int *s_flag)
+                                uint32_t limit, double *tot, double (*s_red)[32], int *s_flag, OnMiss on_miss)
 {
     static_assert(RW == 16 || RW == 32, "row width");
-    constexpr uint32_t RP = kWG / RW;   // rows per pass
+    constexpr int NW = WG / 64;
+    constexpr uint32_t RP = WG / RW;    // rows per pass
     constexpr int KB = 16;              // passes per batch (loads in flight per thread)
     const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -206,12 +214,12 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
         __syncthreads();
         bool anybad = false;
 #pragma unroll
-        for (int q = 0; q < kWaves; ++q) anybad |= s_flag[1 + q] != 0;
+        for (int q = 0; q < NW; ++q) anybad |= s_flag[1 + q] != 0;
         if (!anybad) {
             if (threadIdx.x < NV) {
                 double t = 0.0;
 #pragma unroll
-                for (int q = 0; q < kWaves; ++q) t += s_red[q][threadIdx.x];
+                for (int q = 0; q < NW; ++q) t += s_red[q][threadIdx.x];
                 tot[threadIdx.x] = t;
             }
             __syncthreads();
@@ -221,11 +229,18 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
             if (threadIdx.x == 0) raise_error(err);
             return false;
         }
-        if (threadIdx.x == 0) s_flag[0] = ld_agent(err) != 0u ? 1 : 0;
-        __builtin_amdgcn_s_sleep(1);
-        __syncthreads();
-        if (s_flag[0]) return false;
+        if (!on_miss(it)) return false;
     }
+}
+
+// The default wait between reads of rows: a short sleep; false once another
+// group has raised the error word.  Collective.
+__device__ inline bool rows_backoff(uint32_t *err, int *s_flag)
+{
+    if (threadIdx.x == 0) s_flag[0] = ld_agent(err) != 0u ? 1 : 0;
+    __builtin_amdgcn_s_sleep(1);
+    __syncthreads();
+    return s_flag[0] == 0;
 }
 
 // Thread 0: store the NV values as a tagged row (single-copy-atomic words).
@@ -247,9 +262,9 @@ constexpr uint32_t kFlatMaxGroups = 256;
 // its team's counter; above kFlatMaxGroups the team's last arriver also sums
 // its team's rows into the team row.  The caller may do independent work
 // before the gathering half (allreduce_gather) with the same epoch.  Uses
-// s_flag[1 + kWaves] (the team-last flag), so that the gathering half's flags
-// never overlap it.
-template <int NV, int RW>
+// s_flag[1 + WG / 64] (the team-last flag), so that the gathering half's
+// flags never overlap it.
+template <int NV, int RW, int WG = kWG>
 __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
                                          uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit,
                                          double *tot, double (*s_red)[32], int *s_flag)
@@ -273,13 +288,13 @@ __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, ui
         if (threadIdx.x == 0) {
             const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
-            s_flag[1 + kWaves] = old + 1u == epoch * min(TS, G - tau * TS) ? 1 : 0;
+            s_flag[1 + WG / 64] = old + 1u == epoch * min(TS, G - tau * TS) ? 1 : 0;
         }
         __syncthreads();
-        if (s_flag[1 + kWaves]) {
+        if (s_flag[1 + WG / 64]) {
             const uint32_t first = tau * TS;
-            if (!sum_rows<NV, RW>(slots + (size_t)first * RW, min(TS, G - first), tag, err, limit, tot, s_red,
-                                  s_flag))
+            if (!sum_rows<NV, RW, WG>(slots + (size_t)first * RW, min(TS, G - first), tag, err, limit, tot, s_red,
+                                      s_flag, [&](uint32_t) { return rows_backoff(err, s_flag); }))
                 return false;
             if (threadIdx.x == 0) put_row<NV>(tslots + (size_t)tau * RW, tot, tag);
         }
@@ -288,54 +303,67 @@ __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, ui
 }
 
 // Gathering half: wait until every group (or team) of `epoch` has published,
-// then sum the rows in the fixed order into tot (LDS, every thread).
-template <int NV, int RW>
+// then sum the rows in the fixed order into tot (LDS, every thread).  Flat:
+// wave 0 waits on the team counters, then the rows are read (re-read until
+// every word carries the tag).  With rows_first (a caller that did other
+// work since publishing, so the rows usually all carry the tag already) the
+// rows are read once before the counters, which saves their round trip.
+// Teams: wave 0 waits on the team rows' tags, then the team rows are summed.
+template <int NV, int RW, int WG = kWG>
 __device__ inline bool allreduce_gather(uint32_t G, uint64_t *rows, uint32_t *words, uint32_t *err,
                                         uint32_t epoch, uint32_t limit, double *tot, double (*s_red)[32],
-                                        int *s_flag)
+                                        int *s_flag, bool rows_first = false)
 {
     const uint64_t tag = epoch & 3u;
     uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
     uint64_t *tslots = rows + (size_t)2 * G * RW + (size_t)(epoch & 1u) * kMaxTeams * RW;
     const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
     const bool flat = G <= kFlatMaxGroups;
-    if (threadIdx.x < 64) {
-        // flat: lane t < NT watches team t's counter; teams: lane t watches
-        // team t's row (word 0 carries the epoch tag).  Wave-uniform exit.
-        const uint32_t lane = threadIdx.x;
-        const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
-        uint32_t it = 0;
-        bool ok = true;
-        for (;;) {
-            bool pending;
-            if (flat) {
-                const uint32_t seen = lane < NT ? ld_agent(words + kSyncLine * (1 + lane)) : 0u;
-                pending = seen < want;
-            } else {
-                const uint64_t w0 = lane < NT ? __hip_atomic_load(tslots + (size_t)lane * RW, __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_AGENT)
-                                              : tag;
-                pending = (w0 & 3u) != tag;
+    auto poll = [&]() -> bool {
+        if (threadIdx.x < 64) {
+            // flat: lane t < NT watches team t's counter; teams: lane t
+            // watches team t's row (word 0 carries the epoch tag).
+            // Wave-uniform exit.
+            const uint32_t lane = threadIdx.x;
+            const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
+            uint32_t it = 0;
+            bool ok = true;
+            for (;;) {
+                bool pending;
+                if (flat) {
+                    const uint32_t seen = lane < NT ? ld_agent(words + kSyncLine * (1 + lane)) : 0u;
+                    pending = seen < want;
+                } else {
+                    const uint64_t w0 = lane < NT ? __hip_atomic_load(tslots + (size_t)lane * RW, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                                  : tag;
+                    pending = (w0 & 3u) != tag;
+                }
+                if (__builtin_amdgcn_ballot_w64(pending) == 0) break;
+                if (ld_agent(err) != 0u) { ok = false; break; }
+                if (++it > limit) { if (lane == 0) raise_error(err); ok = false; break; }
+                __builtin_amdgcn_s_sleep(1);
             }
-            if (__builtin_amdgcn_ballot_w64(pending) == 0) break;
-            if (ld_agent(err) != 0u) { ok = false; break; }
-            if (++it > limit) { if (lane == 0) raise_error(err); ok = false; break; }
-            __builtin_amdgcn_s_sleep(1);
+            if (lane == 0) s_flag[0] = ok ? 1 : 0;
         }
-        if (lane == 0) s_flag[0] = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_flag[0]) return false;
-    return sum_rows<NV, RW>(flat ? slots : tslots, flat ? G : NT, tag, err, limit, tot, s_red, s_flag);
+        __syncthreads();
+        return s_flag[0] != 0;
+    };
+    const bool early = flat && rows_first;
+    if (!early && !poll()) return false;
+    return sum_rows<NV, RW, WG>(flat ? slots : tslots, flat ? G : NT, tag, err, limit, tot, s_red, s_flag,
+                                [&](uint32_t attempt) {
+                                    return (early && attempt == 1) ? poll() : rows_backoff(err, s_flag);
+                                });
 }
 
-template <int NV, int RW>
+template <int NV, int RW, int WG = kWG>
 __device__ inline bool allreduce(const double (&v)[NV], uint32_t gid, uint32_t G, uint64_t *rows,
                                  uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit, double *tot,
                                  double (*s_red)[32], int *s_flag)
 {
-    return allreduce_publish<NV, RW>(v, gid, G, rows, words, err, epoch, limit, tot, s_red, s_flag) &&
-           allreduce_gather<NV, RW>(G, rows, words, err, epoch, limit, tot, s_red, s_flag);
+    return allreduce_publish<NV, RW, WG>(v, gid, G, rows, words, err, epoch, limit, tot, s_red, s_flag) &&
+           allreduce_gather<NV, RW, WG>(G, rows, words, err, epoch, limit, tot, s_red, s_flag);
 }
 
 }  // namespace amq
