@@ -16,7 +16,9 @@ namespace amq {
 // every lane, beside the resident cashflows), else LDS; a date with fewer in-the-money
 // paths than p or a pivot below 1e-14 (on the unit-diagonal matrix) allows no
 // exercise.  beta: [0..7] coefficients in the standardised basis (zero past
-// p), [8] solved flag, [9] in-the-money count.
+// p), [8] solved flag, [9] in-the-money count.  Branch-free (a rejected
+// pivot takes the square root of 1 and clears the flag), so the independent
+// square roots of the equilibration overlap.
 template <int D>
 __device__ __forceinline__ void solve_date(const double *tot, double *beta, double (*L)[8], double *w)
 {
@@ -28,7 +30,7 @@ __device__ __forceinline__ void solve_date(const double *tot, double *beta, doub
     for (int i = 0; i < P; ++i) {
         const double d = tot[2 * i];
         ok = ok && (d > 0.0);
-        sc[i] = d > 0.0 ? rsqrt_f64(d) : 0.0;
+        sc[i] = rsqrt_f64(d > 0.0 ? d : 1.0);
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -36,7 +38,7 @@ __device__ __forceinline__ void solve_date(const double *tot, double *beta, doub
 #pragma unroll
         for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
         ok = ok && (d > 1e-14);
-        rl[j] = d > 1e-14 ? rsqrt_f64(d) : 1.0;    // 1 / L[j][j]
+        rl[j] = rsqrt_f64(d > 1e-14 ? d : 1.0);    // 1 / L[j][j]
 #pragma unroll
         for (int i = j + 1; i < P; ++i) {
             double e = tot[i + j] * sc[i] * sc[j];
@@ -291,8 +293,11 @@ __device__ __forceinline__ void solve_and_record(const SweepArgs &a, uint32_t gi
     constexpr int NV = 3 * D + 4;
     const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
     if constexpr (REGS) {
-        double Lr[8][8], wr[32];
-        solve_date<D>(s_tot, s_beta, Lr, wr);
+        // the totals in registers first: every LDS read issued at once
+        double tr[NV], Lr[8][8], wr[32];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) tr[q] = s_tot[q];
+        solve_date<D>(tr, s_beta, Lr, wr);
     } else {
         solve_date<D>(s_tot, s_beta, s_L, s_w);
     }
@@ -324,7 +329,7 @@ template <typename T, int PPT, int D, bool LAG, int WG>
 __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                            const TileIO<T, PPT, WG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                            double (*s_red)[32], double (*s_red2)[32], double *s_tot,
-                                           double *s_beta, double *s_wl, int *s_flag)
+                                           double *s_beta, double *s_wl, double *s_x, int *s_flag)
 {
     using SH = SweepShape<T, PPT>;
     constexpr int VW = SH::VW, NVEC = SH::NVEC;
@@ -380,7 +385,8 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
         for (int q = 0; q < NA; ++q) g[q] += g2[q];
         g[NA] = (double)cnt;
-        group_sum<NG, 1, WG>(g, s_red2);
+        if constexpr (WG == 512 && NA <= 8) group_sum_lds<NG, 1, WG>(g, s_x, s_red2);
+        else group_sum<NG, 1, WG>(g, s_red2);
     };
 
     if (!(a.allow_exercise && M >= 2)) return;
@@ -439,7 +445,8 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int q = 0; q < NB; ++q) rs[q] += r2[q];
         }
-        group_sum<NB, 0, WG>(rs, s_red);
+        if constexpr (WG == 512) group_sum_lds<NB, 0, WG>(rs, s_x, s_red);
+        else group_sum<NB, 0, WG>(rs, s_red);
         ++epoch;
         stamp[0] = __builtin_amdgcn_s_memrealtime();
         double acc[NV];
@@ -602,6 +609,9 @@ struct SweepLds {
     double w[KEEP ? 1 : 32];
     // Laguerre weights of a KEEP tile, [2 dates][path][thread]
     double wl[LAG && KEEP ? 2 * PPT * WG : 1];
+    // component-major partials of the LDS group sums (512-thread groups):
+    // [8][WG]; consecutive sums are separated by barriers
+    double x[KEEP && WG == 512 ? 8 * WG : 1];
     DateConst dc[KEEP ? 1 : kMaxDates + 1];
     int flag[2 + WG / 64];
 };
@@ -614,7 +624,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     const TileIO<T, PPT, WG> io(gid, e0);
     sweep_terminal<T, PPT, WG>(a, S, io, pv);
     if constexpr (SweepShape<T, PPT>::KEEP) {
-        sweep_keep<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.flag);
+        sweep_keep<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.x,
+                                       L.flag);
     } else {
         static_assert(WG == kWG, "streamed tiles run 256-thread groups");
         sweep_stream<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc, L.flag);

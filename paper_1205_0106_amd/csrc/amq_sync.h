@@ -101,6 +101,60 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
     }
 }
 
+// The same sum through LDS for groups with two waves per SIMD: every thread
+// stores its NV - NU components ([8][WG] doubles at s_x), then component q's
+// WG/8 threads each add 8 of them (stride WG/8, ascending) and reduce their
+// partials on the vector unit (a 64-lane wave_sum, or the 32-lane half of it
+// for WG = 256); the wave-uniform components go through s_red as in
+// group_sum.  Fewer vector instructions than a DPP tree per component when
+// NV - NU is large.  Result valid in thread 0.
+template <int NV, int NU, int WG>
+__device__ __forceinline__ void group_sum_lds(double (&v)[NV], double *s_x, double (*s_red)[32])
+{
+    constexpr int NC = NV - NU, TPC = WG / 8;
+    static_assert(NC <= 8 && NV <= 32 && (TPC == 32 || TPC == 64), "component slots");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) s_x[q * WG + tid] = v[q];
+    if (lane == 63) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) s_red[wave][NC + u] = v[NC + u];
+    }
+    __syncthreads();
+    const int q = tid / TPC, l = tid % TPC;
+    double acc = 0.0;
+    if (q < NC) {
+        double x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = s_x[q * WG + l + i * TPC];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc += x[i];
+    }
+    if (TPC == 64) {
+        acc = wave_sum(acc);
+        if (lane == 63 && q < NC) s_red[0][q] = acc;
+    } else {
+        acc = dpp_add<0xB1, 0xF>(acc);
+        acc = dpp_add<0x4E, 0xF>(acc);
+        acc = dpp_add<0x141, 0xF>(acc);
+        acc = dpp_add<0x140, 0xF>(acc);
+        acc = dpp_add<0x142, 0xA>(acc);   // lanes 31 and 63: their half-wave's sum
+        if ((lane & 31) == 31 && q < NC) s_red[0][q] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = s_red[0][c];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            double t = s_red[0][NC + u];
+#pragma unroll
+            for (int w = 1; w < WG / 64; ++w) t += s_red[w][NC + u];
+            v[NC + u] = t;
+        }
+    }
+}
+
 // Fixed-order sum of G partial slots (kPartStride doubles apart) into
 // tot[0..NV-1] (LDS), by the whole workgroup.  Thread t owns component t % 32
 // of groups t/32, t/32 + 8, ...; its loads are issued in batches of 4 before
