@@ -196,7 +196,11 @@ __device__ __forceinline__ T exercise_update(T s_t, T pvj, double sg, double nsk
                                              const double *gam, double wc, const double *wgiven = nullptr)
 {
     constexpr int P = D + 1;
-    const double s = (double)s_t;
+    // recomputed here rather than kept from the moment pass: holding every
+    // path's payoff and abscissa across the sum costs more registers than
+    // the two fmas
+    double s = (double)s_t;
+    asm volatile("" : "+v"(s));
     const double h = payoff_arg(s, sg, nsk);
     const double xs = fma(s, xa, xb);
     double cont = gam[P - 1];

@@ -215,6 +215,32 @@ def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
         assert abs(price - ores.price) <= 0.02 * ores.price + TOL[dtype]
 
 
+@pytest.mark.parametrize("N,M,basis,dtype", [(33001, 9, ("laguerre", 3), "fp64"), (4097, 12, ("laguerre", 2), "fp64"),
+                                             (70000, 17, ("monomial", 2), "fp32"),
+                                             (1 << 18, 20, ("laguerre", 3), "fp32"),
+                                             ((1 << 18) + 999, 6, ("monomial", 3), "fp64")])
+def test_group_size_forms_agree(amq, orc, pricer, N, M, basis, dtype):
+    # register-resident tiles run in 256- or 512-thread groups: both forms
+    # must meet the oracle, with identical in-the-money counts (those depend
+    # on the path values only)
+    kw = dict(S0=100.0, K=104.0, r=0.045, sigma=0.28, T=1.25)
+    ores, od = oracle_price(orc, None, N=N, M=M, basis=basis, **kw)
+    out = []
+    try:
+        for wide in (False, True):
+            amq.am_debug_set_sweep_wide(wide)
+            price, se, v = gpu_price(amq, pricer, None, N=N, M=M, dtype=dtype, basis=basis, **kw)
+            nitm = v["rec"].cpu().numpy()[1:M, 9].astype(np.int64)
+            out.append((price, nitm))
+            log(f"  wide={wide}: gpu {price:.10f} oracle {ores.price:.10f}")
+            assert abs(price - ores.price) <= TOL[dtype]
+    finally:
+        amq.am_debug_set_sweep_wide(True)
+    assert np.array_equal(out[0][1], out[1][1])
+    if dtype == "fp64":
+        assert np.array_equal(out[0][1], od["nitm"][1:M])
+
+
 def test_team_level_device_sum(amq, orc, pricer):
     # more than 256 workgroups: teams sum first; 500 groups of 64 paths per
     # thread leaves a last team of 4 (teams of 16)
