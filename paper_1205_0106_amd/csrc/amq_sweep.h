@@ -558,7 +558,6 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
                     cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], sg, nsk, xa, xb, wc);
-                    __builtin_amdgcn_sched_barrier(0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -588,12 +587,11 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
                 const Vec<T> cur = ring[jj % PD];
                 if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
                 __builtin_amdgcn_sched_barrier(0);
+                // a vector's paths together: their dependent chains interleave
 #pragma unroll
-                for (int e = 0; e < VW; ++e) {
+                for (int e = 0; e < VW; ++e)
                     pv[jj * VW + e] = exercise_update<T, D, LAG>(cur.v[e], pv[jj * VW + e], sg, nsk, xa, xb, dk, gam,
                                                                  wc);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
