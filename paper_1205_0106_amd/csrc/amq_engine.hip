@@ -214,12 +214,13 @@ int groups_per_cu(DevState *st, int fp64, int laguerre, int wg, int ppt, int deg
 }
 
 // Single-option tiles (threads per group, paths per thread).  The 512-thread
-// forms of the register-resident tiles come first, so they win ties with the
-// 256-thread form of the same tile size.
+// forms come first, so they win ties with the 256-thread form of the same
+// tile size (binary32 streamed tiles too: one group of two waves per SIMD
+// instead of two groups, half the groups in the device-wide sum).
 struct TileShape { int wg, ppt; };
-const TileShape kTiles32[] = {{512, 4}, {256, 4}, {512, 8}, {256, 16}, {256, 64}, {256, 128}};
+const TileShape kTiles32[] = {{512, 4}, {256, 4}, {512, 8}, {256, 16}, {512, 64}, {256, 64}, {512, 128}, {256, 128}};
 const TileShape kTiles64[] = {{512, 2}, {256, 2}, {512, 4}, {256, 8}, {256, 16}, {256, 64}};
-const int kNTiles = 6;
+const int kNTiles32 = 8, kNTiles64 = 6;
 thread_local int32_t g_sweep_wide = 1;   // 0: single-option sweeps use 256-thread groups only
 
 // Tile choice for one sweep.  Every date costs one device-wide sum, whose
@@ -230,9 +231,10 @@ thread_local int32_t g_sweep_wide = 1;   // 0: single-option sweeps use 256-thre
 int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Plan *p)
 {
     const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
+    const int n_tiles = fp64 ? kNTiles64 : kNTiles32;
     double best = 0.0;
     bool found = false;
-    for (int i = 0; i < kNTiles; ++i) {
+    for (int i = 0; i < n_tiles; ++i) {
         const int wg = tiles[i].wg, ppt = tiles[i].ppt;
         if (wg != amq::kWG && !g_sweep_wide) continue;
         const int per_cu = groups_per_cu(st, fp64, laguerre, wg, ppt, degree);
@@ -240,6 +242,11 @@ int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Pla
         int64_t gmax = (int64_t)per_cu * st->num_cu;
         if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
         const int64_t tile = (int64_t)wg * ppt;
+        // the tiles must cover whole padded rows (a tile reads every path it
+        // covers): tiles larger than the row padding only where they divide
+        // the padded row length
+        const int64_t ld = (N + amq::kLdAlign - 1) / amq::kLdAlign * amq::kLdAlign;
+        if (ld % tile != 0) continue;
         const int64_t G = (N + tile - 1) / tile;
         if (G > gmax) continue;
         // per-date work: ~40 lane operations per path (binary64: ~2x) at
@@ -405,8 +412,9 @@ int64_t am_max_paths(int32_t dtype)
     if (get_state(&st)) return 0;
     const int fp64 = dtype == AM_FP64;
     const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
+    const int n_tiles = fp64 ? kNTiles64 : kNTiles32;
     int64_t best = 0;
-    for (int i = 0; i < kNTiles; ++i) {
+    for (int i = 0; i < n_tiles; ++i) {
         int64_t worst = -1;
         for (int d = 0; d < 2 * (AM_MAX_DEGREE + 1); ++d) {
             int64_t g = (int64_t)groups_per_cu(st, fp64, d & 1, tiles[i].wg, tiles[i].ppt, d >> 1) * st->num_cu;

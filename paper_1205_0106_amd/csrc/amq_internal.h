@@ -34,7 +34,9 @@ __host__ __device__ constexpr int row_words(int degree) { return 3 * degree + 3 
 constexpr int kMaxRowWords = 32;
 // group rows [2][G][row_words] then team rows [2][kMaxTeams][row_words]
 __host__ __device__ inline int64_t rows_words(int64_t G, int degree) { return 2 * (G + kMaxTeams) * row_words(degree); }
-constexpr int64_t kLdAlign = 32768;  // row padding: a multiple of every sweep tile (256 * PPT)
+// row padding: a multiple of every sweep tile up to 32768 paths; the
+// 65536-path tile is used only where it divides the padded row
+constexpr int64_t kLdAlign = 32768;
 
 // One node of the Brownian bridge, in depth-first construction order.  The
 // value of W at date m (in units of sqrt(dt)) is

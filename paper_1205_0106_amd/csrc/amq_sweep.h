@@ -513,9 +513,9 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 // Streamed tile: the date's slab is read twice (moments, then update)
 // through a ring of PD vector loads in flight per thread; date constants
 // staged in LDS.
-template <typename T, int PPT, int D, bool LAG>
+template <typename T, int PPT, int D, bool LAG, int WG>
 __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
-                                             const TileIO<T, PPT, kWG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
+                                             const TileIO<T, PPT, WG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                              double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
                                              double *s_w, DateConst *s_dc, int *s_flag)
 {
@@ -533,7 +533,7 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
     if (!(a.allow_exercise && a.M >= 2)) return;
     // date constants staged in LDS (a dependent global load at the top of
     // each date would stall the moment pass)
-    for (int k = tid; k <= a.M; k += kWG) s_dc[k] = a.datec[k];
+    for (int k = tid; k <= a.M; k += WG) s_dc[k] = a.datec[k];
     __syncthreads();
     for (int k = a.M - 1; k >= 1; --k) {
         const double xa = uniform_f64(s_dc[k].xa), xb = uniform_f64(s_dc[k].xb),
@@ -564,11 +564,11 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
         }
         acc[NV - 1] = (double)cnt;
 
-        group_sum<NV>(acc, s_red);
+        group_sum<NV, 0, WG>(acc, s_red);
         ++epoch;
         // (a clock read before group_sum would pin the moment pass's schedule)
         stamp[0] = stamp[1] = __builtin_amdgcn_s_memrealtime();
-        if (!allreduce<NV, RW>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
+        if (!allreduce<NV, RW, WG>(acc, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
             alive = false;
             return;
         }
@@ -629,8 +629,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
         sweep_keep<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.x,
                                        L.flag);
     } else {
-        static_assert(WG == kWG, "streamed tiles run 256-thread groups");
-        sweep_stream<T, PPT, D, LAG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc, L.flag);
+        sweep_stream<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc,
+                                         L.flag);
     }
 }
 
@@ -812,7 +812,7 @@ inline const void *sweep_entry(int degree)
 }
 
 // Paths per thread built.  binary32: 4, 16, 64, 128 (256-thread groups),
-// 4, 8 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4
+// 4, 8, 64, 128 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4
 // (512), batch 2, 8.
 template <typename T, bool LAG>
 inline const void *sweep_table(int ppt, int degree, int kind)
@@ -851,6 +851,8 @@ inline const void *sweep_table(int ppt, int degree, int kind)
             switch (ppt) {
             case 4: return sweep_entry<T, 4, LAG, 2>(degree);
             case 8: return sweep_entry<T, 8, LAG, 2>(degree);
+            case 64: return sweep_entry<T, 64, LAG, 2>(degree);
+            case 128: return sweep_entry<T, 128, LAG, 2>(degree);
             default: return nullptr;
             }
         }

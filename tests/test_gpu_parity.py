@@ -218,11 +218,13 @@ def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
 @pytest.mark.parametrize("N,M,basis,dtype", [(33001, 9, ("laguerre", 3), "fp64"), (4097, 12, ("laguerre", 2), "fp64"),
                                              (70000, 17, ("monomial", 2), "fp32"),
                                              (1 << 18, 20, ("laguerre", 3), "fp32"),
-                                             ((1 << 18) + 999, 6, ("monomial", 3), "fp64")])
+                                             ((1 << 18) + 999, 6, ("monomial", 3), "fp64"),
+                                             ((1 << 23) - 5, 5, ("monomial", 3), "fp32")])
 def test_group_size_forms_agree(amq, orc, pricer, N, M, basis, dtype):
-    # register-resident tiles run in 256- or 512-thread groups: both forms
-    # must meet the oracle, with identical in-the-money counts (those depend
-    # on the path values only)
+    # tiles run in 256- or 512-thread groups (register-resident tiles, and
+    # binary32 streamed tiles of 2^23 paths and more): both forms must meet
+    # the oracle, with identical in-the-money counts (those depend on the
+    # path values only)
     kw = dict(S0=100.0, K=104.0, r=0.045, sigma=0.28, T=1.25)
     ores, od = oracle_price(orc, None, N=N, M=M, basis=basis, **kw)
     out = []
