@@ -102,6 +102,17 @@ struct SweepShape {
     static constexpr int waves() { return (sizeof(T) * PPT <= 16 && !LAG && D <= 2) ? 4 : 2; }
 };
 
+// Vectors of a streamed tile's date slab kept in LDS between the moment pass
+// and the exercise update (one group of 512 threads per CU: up to 128 KiB),
+// so the update reads only the rest from memory again.
+template <typename T, int PPT, int WG>
+constexpr int stream_keep_vecs()
+{
+    if (SweepShape<T, PPT>::KEEP || WG != 512) return 0;
+    constexpr int cap = (128 * 1024) / (WG * 16);
+    return SweepShape<T, PPT>::NVEC < cap ? SweepShape<T, PPT>::NVEC : cap;
+}
+
 // The per-path arithmetic of the sweep is binary64 for both storage types
 // (path values and cashflows are stored in T): the least-squares fit and the
 // exercise test feed back into every later date, and binary32 arithmetic
@@ -517,8 +528,9 @@ template <typename T, int PPT, int D, bool LAG, int WG>
 __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                              const TileIO<T, PPT, WG> &io, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                              double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
-                                             double *s_w, DateConst *s_dc, int *s_flag)
+                                             double *s_w, DateConst *s_dc, Vec<T> *s_keep, int *s_flag)
 {
+    constexpr int NK = stream_keep_vecs<T, PPT, WG>();
     using SH = SweepShape<T, PPT>;
     constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
     constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
@@ -555,6 +567,7 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
                 const Vec<T> cur = ring[jj % PD];
                 if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
                 __builtin_amdgcn_sched_barrier(0);
+                if (jj < NK) s_keep[jj * WG + tid] = cur;   // the update reads these back
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
                     cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], sg, nsk, xa, xb, wc);
@@ -579,13 +592,22 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
             double gam[P];
 #pragma unroll
             for (int q = 0; q < P; ++q) gam[q] = s_beta[q];
+            // the vectors kept in LDS first, with the memory ring for the
+            // rest already in flight
             Vec<T> ring[PD];
 #pragma unroll
-            for (int q = 0; q < PD; ++q) ring[q] = io.load(row, q);
+            for (int q = 0; q < PD; ++q)
+                if (NK + q < NVEC) ring[q] = io.load(row, NK + q);
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
-                const Vec<T> cur = ring[jj % PD];
-                if (jj + PD < NVEC) ring[jj % PD] = io.load(row, jj + PD);
+                Vec<T> cur;
+                if (jj < NK) {
+                    cur = s_keep[jj * WG + tid];
+                } else {
+                    const int r = (jj - NK) % PD;
+                    cur = ring[r];
+                    if (jj + PD < NVEC) ring[r] = io.load(row, jj + PD);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 // a vector's paths together: their dependent chains interleave
 #pragma unroll
@@ -615,6 +637,9 @@ struct SweepLds {
     // [8][WG]; consecutive sums are separated by barriers
     double x[KEEP && WG == 512 ? 8 * WG : 1];
     DateConst dc[KEEP ? 1 : kMaxDates + 1];
+    // streamed tiles: the first vectors of each thread's slab, kept from the
+    // moment pass for the update ([vector][thread])
+    Vec<T> keep[stream_keep_vecs<T, PPT, WG>() > 0 ? stream_keep_vecs<T, PPT, WG>() * WG : 1];
     int flag[2 + WG / 64];
 };
 
@@ -630,7 +655,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
                                        L.flag);
     } else {
         sweep_stream<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc,
-                                         L.flag);
+                                         L.keep, L.flag);
     }
 }
 
