@@ -94,6 +94,80 @@ __device__ __forceinline__ double inv_normal_f64(uint32_t x)
     return y < 0.0 ? -v : v;
 }
 
+// The same two branches separately, for the compacted evaluation in the
+// path generator: which branch a point takes, the central rational function
+// and the tail polynomial (bitwise the values inv_normal_f32/_f64 return).
+template <typename T> struct MoroParts;
+
+template <> struct MoroParts<float> {
+    static __device__ __forceinline__ bool tail(uint32_t x)
+    {
+        const float y = (float)(int32_t)(x - 0x80000000u) * 0x1p-32f;
+        return !(fabsf(y) < 0.42f);
+    }
+    static __device__ __forceinline__ float central(uint32_t x)
+    {
+        const float y = (float)(int32_t)(x - 0x80000000u) * 0x1p-32f;
+        const float r = y * y;
+        const float num = y * fmaf(fmaf(fmaf((float)AMQ_A3, r, (float)AMQ_A2), r, (float)AMQ_A1), r,
+                                   (float)AMQ_A0);
+        const float den = fmaf(fmaf(fmaf(fmaf((float)AMQ_B3, r, (float)AMQ_B2), r, (float)AMQ_B1), r,
+                                    (float)AMQ_B0), r, 1.0f);
+        return num * __builtin_amdgcn_rcpf(den);
+    }
+    static __device__ __forceinline__ float tail_value(uint32_t x)
+    {
+        const int32_t d = (int32_t)(x - 0x80000000u);
+        const uint32_t tq = d < 0 ? x : 0u - x;
+        const float q = (float)tq * 0x1p-32f;
+        const float ln2 = 0.69314718055994531f;
+        const float t = __builtin_amdgcn_logf(-__builtin_amdgcn_logf(q) * ln2) * ln2;
+        float v = (float)AMQ_C8;
+        v = fmaf(v, t, (float)AMQ_C7);
+        v = fmaf(v, t, (float)AMQ_C6);
+        v = fmaf(v, t, (float)AMQ_C5);
+        v = fmaf(v, t, (float)AMQ_C4);
+        v = fmaf(v, t, (float)AMQ_C3);
+        v = fmaf(v, t, (float)AMQ_C2);
+        v = fmaf(v, t, (float)AMQ_C1);
+        v = fmaf(v, t, (float)AMQ_C0);
+        return d < 0 ? -v : v;
+    }
+};
+
+template <> struct MoroParts<double> {
+    static __device__ __forceinline__ bool tail(uint32_t x)
+    {
+        const double y = ((double)x - 2147483648.0) * 0x1p-32;
+        return !(fabs(y) < 0.42);
+    }
+    static __device__ __forceinline__ double central(uint32_t x)
+    {
+        const double y = ((double)x - 2147483648.0) * 0x1p-32;
+        const double r = y * y;
+        const double num = y * (((AMQ_A3 * r + AMQ_A2) * r + AMQ_A1) * r + AMQ_A0);
+        const double den = (((AMQ_B3 * r + AMQ_B2) * r + AMQ_B1) * r + AMQ_B0) * r + 1.0;
+        return num / den;
+    }
+    static __device__ __forceinline__ double tail_value(uint32_t x)
+    {
+        const double s = 0x1p-32;
+        const double y = ((double)x - 2147483648.0) * s;
+        const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
+        const double t = log(-log(q));
+        double v = AMQ_C8;
+        v = v * t + AMQ_C7;
+        v = v * t + AMQ_C6;
+        v = v * t + AMQ_C5;
+        v = v * t + AMQ_C4;
+        v = v * t + AMQ_C3;
+        v = v * t + AMQ_C2;
+        v = v * t + AMQ_C1;
+        v = v * t + AMQ_C0;
+        return y < 0.0 ? -v : v;
+    }
+};
+
 // Shifted (randomised) points sit at cell midpoints u = (x + 1/2) 2^-32, so a
 // shifted integer 0 still maps to a finite normal.
 __device__ __forceinline__ float inv_normal_mid_f32(uint32_t x)
@@ -154,9 +228,18 @@ template <> __device__ __forceinline__ double inv_normal<double, false>(uint32_t
 template <> __device__ __forceinline__ float inv_normal<float, true>(uint32_t x) { return inv_normal_mid_f32(x); }
 template <> __device__ __forceinline__ double inv_normal<double, true>(uint32_t x) { return inv_normal_mid_f64(x); }
 
-size_t generate_lds_bytes(int M)
+// Nodes whose tail normals are evaluated together (binary64 paths): a
+// 64-point Sobol block puts about 10 of its 64 points of each dimension in
+// the tails (|u - 1/2| >= 0.42), so the tails of 5 nodes mostly fill one wave.
+constexpr int kTailChunk = 5;
+
+size_t generate_lds_bytes(int M, int fp64)
 {
-    return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t);
+    // lane tables [M][16], per-wave block words [kWaves][M][2]; binary64:
+    // per-wave tail staging, points [kTailChunk * 64] u32 and normals
+    // [kTailChunk * 64] f64
+    return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t) +
+           (fp64 ? (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -188,6 +271,12 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t *ttab = lds;                                   // [M][16]
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
+    // this wave's tail staging (see kTailChunk)
+    uint32_t *tx = lds + (size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)wave * kTailChunk * 64;
+    T *tz = reinterpret_cast<T *>(reinterpret_cast<char *>(lds) +
+                                  (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * kTailChunk * 64) *
+                                       sizeof(uint32_t) + 7) / 8 * 8) +
+            (size_t)wave * kTailChunk * 64;
 
     if (init && WHAT == 0) {
         for (int q = tid; q < kSyncWords; q += kWG) a.sync[q] = 0u;
@@ -285,6 +374,71 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             for (int m = 0; m < M; ++m) ((T *)a.S)[(size_t)m * a.ld + i] = Kp;
             continue;
         }
+        if constexpr (WHAT == 0 && !MID && sizeof(T) == 8) {
+            // binary64 paths: the inverse normal's two branches evaluated
+            // apart (the tail's two library logarithms dominate; in binary32,
+            // with hardware logarithms, evaluating both branches in every lane
+            // is cheaper than the packing).  Every
+            // lane evaluates the (cheap) central branch; the points in the tails
+            // of kTailChunk nodes are packed into this wave's LDS staging
+            // (ballot and lane rank), their tail values evaluated together,
+            // one point per lane, and read back by their owners.  The values
+            // are exactly those of inv_normal.
+            for (int s0 = 0; s0 < M; s0 += kTailChunk) {
+                uint32_t xs[kTailChunk], slot[kTailChunk];
+                bool tl[kTailChunk];
+                uint32_t ntail = 0;   // wave-uniform
+#pragma unroll
+                for (int q = 0; q < kTailChunk; ++q) {
+                    tl[q] = false;
+                    if (s0 + q < M) {
+                        const int j = __builtin_amdgcn_readfirstlane(sched[s0 + q].dim);
+                        const uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
+                        xs[q] = x;
+                        tl[q] = MoroParts<T>::tail(x);
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(tl[q]);
+                        slot[q] = ntail + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (tl[q]) tx[slot[q]] = x;
+                        ntail += (uint32_t)__builtin_popcountll(m);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (uint32_t t0 = 0; t0 < ntail; t0 += 64) {
+                    const uint32_t t = t0 + (uint32_t)lane;
+                    if (t < ntail) tz[t] = MoroParts<T>::tail_value(tx[t]);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int q = 0; q < kTailChunk; ++q) {
+                    if (s0 + q < M) {
+                        const BridgeNode &nd = sched[s0 + q];
+                        const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
+                        const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl),
+                                  n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
+                                  n_dst = __builtin_amdgcn_readfirstlane(nd.dst);
+                        const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr),
+                                     n_sd = uniform_f64(nd.sd);
+                        const T zc = MoroParts<T>::central(xs[q]);
+                        const T z = tl[q] ? tz[slot[q]] : zc;
+                        const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
+                        W[n_dst] = wv;
+                        const double e = mu * (double)n_m + vol * wv;
+                        const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp(e)));
+                        ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
+                    }
+                }
+                // the next chunk rewrites the staging only after every lane
+                // has read its values back
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        } else
         for (int s = 0; s < M; ++s) {
             // node fields moved to scalar registers: the batch kernel reaches
             // the schedule through a loaded descriptor, and a window index the
@@ -330,10 +484,13 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     }
 }
 
-// four waves per SIMD (at most 128 VGPRs): latency hiding for the per-lane
-// dependency chain of each path through the dates
+// four waves per SIMD for binary32 storage (at most 128 VGPRs), three for
+// binary64 (its packed tail evaluation with the library logarithm needs the
+// room):
+// latency hiding for the per-lane dependency chain of each path through the
+// dates
 template <typename T, int WHAT, bool MID>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
            const uint32_t *__restrict__ shift)
 {
@@ -351,7 +508,7 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
 {
     const int64_t waves = (a.nblocks + a.R - 1) / a.R;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
-    const size_t lds = generate_lds_bytes(a.M);
+    const size_t lds = generate_lds_bytes(a.M, fp64);
     const dim3 g((unsigned)grid), b(kWG);
     const bool mid = a.shift != nullptr;
     if (a.what == 0) {
@@ -473,7 +630,7 @@ __device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ units,
                  const uint32_t *__restrict__ V, uint32_t *gsync)
 {
@@ -493,7 +650,7 @@ hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
                                  hipStream_t s)
 {
-    const size_t lds = generate_lds_bytes(max_dates);
+    const size_t lds = generate_lds_bytes(max_dates, fp64);
     if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
     else      hipLaunchKernelGGL((gen_batch_kernel<float>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
     return hipGetLastError();
