@@ -219,8 +219,8 @@ int groups_per_cu(DevState *st, int fp64, int laguerre, int wg, int ppt, int deg
 // instead of two groups, half the groups in the device-wide sum).
 struct TileShape { int wg, ppt; };
 const TileShape kTiles32[] = {{512, 4}, {256, 4}, {512, 8}, {256, 16}, {512, 64}, {256, 64}, {512, 128}, {256, 128}};
-const TileShape kTiles64[] = {{512, 2}, {256, 2}, {512, 4}, {256, 8}, {256, 16}, {256, 64}};
-const int kNTiles32 = 8, kNTiles64 = 6;
+const TileShape kTiles64[] = {{512, 2}, {256, 2}, {512, 4}, {256, 8}, {512, 8}, {256, 16}, {256, 64}};
+const int kNTiles32 = 8, kNTiles64 = 7;
 thread_local int32_t g_sweep_wide = 1;   // 0: single-option sweeps use 256-thread groups only
 
 // Tile choice for one sweep.  Every date costs one device-wide sum, whose

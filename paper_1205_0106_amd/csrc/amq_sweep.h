@@ -837,8 +837,8 @@ inline const void *sweep_entry(int degree)
 }
 
 // Paths per thread built.  binary32: 4, 16, 64, 128 (256-thread groups),
-// 4, 8, 64, 128 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4
-// (512), batch 2, 8.
+// 4, 8, 64, 128 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4,
+// 8 (512), batch 2, 8.
 template <typename T, bool LAG>
 inline const void *sweep_table(int ppt, int degree, int kind)
 {
@@ -854,6 +854,7 @@ inline const void *sweep_table(int ppt, int degree, int kind)
             switch (ppt) {
             case 2: return sweep_entry<T, 2, LAG, 2>(degree);
             case 4: return sweep_entry<T, 4, LAG, 2>(degree);
+            case 8: return sweep_entry<T, 8, LAG, 2>(degree);
             default: return nullptr;
             }
         }
