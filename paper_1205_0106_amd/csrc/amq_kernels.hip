@@ -39,64 +39,9 @@ namespace amq {
 #define AMQ_C7 0.0000002888167364
 #define AMQ_C8 0.0000003960315187
 
-// binary32: both branches are evaluated (every 64-point Sobol block has tail
-// lanes), hardware log2/rcp; y and q come exactly from the 32-bit integer.
-__device__ __forceinline__ float inv_normal_f32(uint32_t x)
-{
-    const float s = 0x1p-32f;
-    const int32_t d = (int32_t)(x - 0x80000000u);
-    const float y = (float)d * s;
-    const float r = y * y;
-    const float num = y * fmaf(fmaf(fmaf((float)AMQ_A3, r, (float)AMQ_A2), r, (float)AMQ_A1), r,
-                               (float)AMQ_A0);
-    const float den = fmaf(fmaf(fmaf(fmaf((float)AMQ_B3, r, (float)AMQ_B2), r, (float)AMQ_B1), r,
-                                (float)AMQ_B0), r, 1.0f);
-    const float zc = num * __builtin_amdgcn_rcpf(den);
-    const uint32_t tq = d < 0 ? x : 0u - x;          // tail integer: x or 2^32 - x
-    const float q = (float)tq * s;
-    const float ln2 = 0.69314718055994531f;
-    const float t = __builtin_amdgcn_logf(-__builtin_amdgcn_logf(q) * ln2) * ln2;
-    float v = (float)AMQ_C8;
-    v = fmaf(v, t, (float)AMQ_C7);
-    v = fmaf(v, t, (float)AMQ_C6);
-    v = fmaf(v, t, (float)AMQ_C5);
-    v = fmaf(v, t, (float)AMQ_C4);
-    v = fmaf(v, t, (float)AMQ_C3);
-    v = fmaf(v, t, (float)AMQ_C2);
-    v = fmaf(v, t, (float)AMQ_C1);
-    v = fmaf(v, t, (float)AMQ_C0);
-    const float zt = d < 0 ? -v : v;
-    return fabsf(y) < 0.42f ? zc : zt;
-}
-
-// binary64: u, u - 1/2 and 1 - u are exact for u = x 2^-32.
-__device__ __forceinline__ double inv_normal_f64(uint32_t x)
-{
-    const double s = 0x1p-32;
-    const double y = ((double)x - 2147483648.0) * s;
-    if (fabs(y) < 0.42) {
-        const double r = y * y;
-        const double num = y * (((AMQ_A3 * r + AMQ_A2) * r + AMQ_A1) * r + AMQ_A0);
-        const double den = (((AMQ_B3 * r + AMQ_B2) * r + AMQ_B1) * r + AMQ_B0) * r + 1.0;
-        return num / den;
-    }
-    const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
-    const double t = log(-log(q));
-    double v = AMQ_C8;
-    v = v * t + AMQ_C7;
-    v = v * t + AMQ_C6;
-    v = v * t + AMQ_C5;
-    v = v * t + AMQ_C4;
-    v = v * t + AMQ_C3;
-    v = v * t + AMQ_C2;
-    v = v * t + AMQ_C1;
-    v = v * t + AMQ_C0;
-    return y < 0.0 ? -v : v;
-}
-
-// The same two branches separately, for the compacted evaluation in the
-// path generator: which branch a point takes, the central rational function
-// and the tail polynomial (bitwise the values inv_normal_f32/_f64 return).
+// The two branches separately: which branch a point takes, the central
+// rational function and the tail polynomial.  inv_normal_f32/_f64 combine
+// them; the binary64 path generator evaluates the tails packed.
 template <typename T> struct MoroParts;
 
 template <> struct MoroParts<float> {
@@ -147,7 +92,7 @@ template <> struct MoroParts<double> {
         const double r = y * y;
         const double num = y * (((AMQ_A3 * r + AMQ_A2) * r + AMQ_A1) * r + AMQ_A0);
         const double den = (((AMQ_B3 * r + AMQ_B2) * r + AMQ_B1) * r + AMQ_B0) * r + 1.0;
-        return num / den;
+        return num * rcp_f64(den);   // (a tail point's value is discarded)
     }
     static __device__ __forceinline__ double tail_value(uint32_t x)
     {
@@ -167,6 +112,20 @@ template <> struct MoroParts<double> {
         return y < 0.0 ? -v : v;
     }
 };
+
+// binary32: both branches are evaluated (every 64-point Sobol block has tail
+// lanes), hardware log2/rcp; y and q come exactly from the 32-bit integer.
+__device__ __forceinline__ float inv_normal_f32(uint32_t x)
+{
+    const float zc = MoroParts<float>::central(x), zt = MoroParts<float>::tail_value(x);
+    return MoroParts<float>::tail(x) ? zt : zc;
+}
+
+// binary64: u, u - 1/2 and 1 - u are exact for u = x 2^-32.
+__device__ __forceinline__ double inv_normal_f64(uint32_t x)
+{
+    return MoroParts<double>::tail(x) ? MoroParts<double>::tail_value(x) : MoroParts<double>::central(x);
+}
 
 // Shifted (randomised) points sit at cell midpoints u = (x + 1/2) 2^-32, so a
 // shifted integer 0 still maps to a finite normal.
@@ -428,7 +387,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                         const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
                         W[n_dst] = wv;
                         const double e = mu * (double)n_m + vol * wv;
-                        const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp(e)));
+                        const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp_poly(e)));
                         ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
                     }
                 }
@@ -464,7 +423,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
             W[n_dst] = wv;
             const double e = mu * (double)n_m + vol * wv;
-            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp(e)));
+            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp_poly(e)));
             ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {
