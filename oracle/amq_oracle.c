@@ -20,8 +20,7 @@
  *   - the Black–Scholes closed form of eqs. (1)-(5) and a CRR binomial tree
  *     (the lattice method named in Section III.E) as independent checks.
  *
- * Readings where the paper is silent or garbled (each also listed in
- * the design doc):
+ * Readings where the paper is silent or garbled:
  *   - dates t_k = kT/M, k = 1..M, so t_M = T (Section V states t_m = T);
  *   - Sobol sequence, Joe–Kuo direction numbers, Gray-code order, point
  *     index 0 skipped (path i uses index i+1); dimension j feeds bridge
@@ -34,7 +33,7 @@
  *     or a numerically rank-deficient design, allows no exercise;
  *   - exercise at t0 is allowed in American mode: price = max(h(S0), mean).
  *
- * Parity pins for every function live in tests/ (see the design doc for the list).
+ * Parity pins for every function live in tests/ (test_oracle_*.py).
  */
 #include "amq_oracle.h"
 

@@ -13,6 +13,10 @@
 
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 namespace amq {
 
 // ---------------------------------------------------------------------------
@@ -518,18 +522,27 @@ int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree)
 // Dynamic LDS that leaves room for one workgroup of `f` per CU (more than
 // half of a CU's LDS in total), so a grid of at most one group per CU is
 // spread over the CUs instead of doubling up on some; 0 if unavailable.
-static size_t one_per_cu_lds(const void *f)
+// Computed once per (device, kernel).
+static size_t one_per_cu_lds(int dev, const void *f)
 {
-    int dev = 0, lds_cu = 0;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, f);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int lds_cu = 0;
     hipFuncAttributes fa;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
-        hipFuncGetAttributes(&fa, f) != hipSuccess)
-        return 0;
-    const size_t want = (size_t)lds_cu / 2 + 1024;
-    if (fa.sharedSizeBytes >= want) return 0;
-    const size_t dyn = want - fa.sharedSizeBytes;
-    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) return 0;
+    size_t dyn = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        hipFuncGetAttributes(&fa, f) == hipSuccess) {
+        const size_t want = (size_t)lds_cu / 2 + 1024;
+        if (fa.sharedSizeBytes < want) {
+            dyn = want - fa.sharedSizeBytes;
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) dyn = 0;
+        }
+    }
+    cache[key] = dyn;
     return dyn;
 }
 
@@ -545,7 +558,7 @@ hipError_t launch_sweep(const SweepArgs &a, int fp64, int wg, int ppt, hipStream
     size_t dyn = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && a.G <= cus)
-        dyn = one_per_cu_lds(f);
+        dyn = one_per_cu_lds(dev, f);
     return hipLaunchCooperativeKernel(f, dim3((unsigned)a.G), dim3((unsigned)wg), params, (unsigned)dyn, s);
 }
 
