@@ -219,7 +219,8 @@ def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
                                              (70000, 17, ("monomial", 2), "fp32"),
                                              (1 << 18, 20, ("laguerre", 3), "fp32"),
                                              ((1 << 18) + 999, 6, ("monomial", 3), "fp64"),
-                                             ((1 << 23) - 5, 5, ("monomial", 3), "fp32")])
+                                             ((1 << 23) - 5, 5, ("monomial", 3), "fp32"),
+                                             ((1 << 23) + 4097, 4, ("laguerre", 2), "fp32")])
 def test_group_size_forms_agree(amq, orc, pricer, N, M, basis, dtype):
     # tiles run in 256- or 512-thread groups (register-resident tiles, and
     # binary32 streamed tiles of 2^23 paths and more): both forms must meet
