@@ -164,9 +164,9 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
 // weight for rhs_add and the exercise update.
 template <int D, bool LAG>
 __device__ __forceinline__ bool gram_add(double *acc, double s, double sg, double nsk, double xa, double xb,
-                                         double wc, double *wout)
+                                         double wc, double *wout, double *yout = nullptr)
 {
-    constexpr int NA = 2 * D + 1;
+    constexpr int NA = 2 * D + 1, NB = D + 1;
     const bool itm = payoff_arg(s, sg, nsk) > 0.0;
     const double xs = fma(s, xa, xb);
     double w = 1.0;
@@ -177,6 +177,7 @@ __device__ __forceinline__ bool gram_add(double *acc, double s, double sg, doubl
     double y = itm ? w : 0.0;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
+        if (yout && q < NB) yout[q] = y;   // the right-hand side's factors, kept for its pass
         acc[q] = LAG ? fma(w, y, acc[q]) : acc[q] + y;
         if (q + 1 < NA) y *= xs;
     }
@@ -375,6 +376,11 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
     // into two accumulator sets (independent chains), pinned per pair; the
     // in-the-money count from wave ballots (scalar unit); result (group
     // total) valid in thread 0
+    // kCacheY: the Gram pass also keeps each path's right-hand-side factors
+    // y_q (q <= D) in registers, so the right-hand-side pass after the update
+    // is one fma per sum (512-thread binary32 tiles, which have the room)
+    constexpr bool kCacheY = WG == 512 && sizeof(T) == 4 && PPT * NB <= 32;
+    double ys[kCacheY ? PPT : 1][NB];
     auto gram_pass = [&](const Vec<T>(&v)[NVEC], double xa, double xb, double *wl, double (&g)[NG]) {
         double g2[NA];
 #pragma unroll
@@ -385,9 +391,10 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int e = 0; e < VW; e += 2) {
                 const int j0 = jj * VW + e;
-                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * WG);
-                const bool i1 =
-                    gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc, wl + (j0 + 1) * WG);
+                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * WG,
+                                                 kCacheY ? ys[kCacheY ? j0 : 0] : nullptr);
+                const bool i1 = gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc,
+                                                 wl + (j0 + 1) * WG, kCacheY ? ys[kCacheY ? j0 + 1 : 0] : nullptr);
                 cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i0)) +
                        (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i1));
 #pragma unroll
@@ -442,14 +449,23 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
             const double *wl = wbuf(k);
             double wv[PPT];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) wv[j] = LAG ? wl[j * WG] : 1.0;
+            for (int j = 0; j < PPT; ++j) wv[j] = (LAG && !kCacheY) ? wl[j * WG] : 1.0;
 #pragma unroll
             for (int jj = 0; jj < NVEC; ++jj) {
 #pragma unroll
                 for (int e = 0; e < VW; e += 2) {
                     const int j0 = jj * VW + e;
-                    rhs_add<D>(rs, (double)sc[jj].v[e], (double)pv[j0], sg, nsk, xa, xb, wv[j0]);
-                    rhs_add<D>(r2, (double)sc[jj].v[e + 1], (double)pv[j0 + 1], sg, nsk, xa, xb, wv[j0 + 1]);
+                    if constexpr (kCacheY) {
+                        // the same products as rhs_add, from the kept factors
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) {
+                            rs[q] = fma((double)pv[j0], ys[j0][q], rs[q]);
+                            r2[q] = fma((double)pv[j0 + 1], ys[j0 + 1][q], r2[q]);
+                        }
+                    } else {
+                        rhs_add<D>(rs, (double)sc[jj].v[e], (double)pv[j0], sg, nsk, xa, xb, wv[j0]);
+                        rhs_add<D>(r2, (double)sc[jj].v[e + 1], (double)pv[j0 + 1], sg, nsk, xa, xb, wv[j0 + 1]);
+                    }
 #pragma unroll
                     for (int q = 0; q < NB; ++q) {
                         asm volatile("" : "+v"(rs[q]));
