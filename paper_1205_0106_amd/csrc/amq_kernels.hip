@@ -191,12 +191,18 @@ template <> __device__ __forceinline__ double inv_normal<double, false>(uint32_t
 template <> __device__ __forceinline__ float inv_normal<float, true>(uint32_t x) { return inv_normal_mid_f32(x); }
 template <> __device__ __forceinline__ double inv_normal<double, true>(uint32_t x) { return inv_normal_mid_f64(x); }
 
+// A bridge node as the batch generator keeps it in LDS.
+struct LdsNode {
+    int32_t dim, m, sl, sr, dst, pad;
+    double wl, wr, sd;
+};
+
 // Nodes whose tail normals are evaluated together (binary64 paths): a
 // 64-point Sobol block puts about 10 of its 64 points of each dimension in
 // the tails (|u - 1/2| >= 0.42), so the tails of 5 nodes mostly fill one wave.
 constexpr int kTailChunk = 5;
 
-size_t generate_lds_bytes(int M, int fp64)
+__host__ __device__ size_t generate_lds_bytes(int M, int fp64)
 {
     // lane tables [M][16], per-wave block words [kWaves][M][2]; binary64:
     // per-wave tail staging, points [kTailChunk * 64] u32 and normals
@@ -223,9 +229,9 @@ size_t generate_lds_bytes(int M, int fp64)
 // One workgroup's share: `init` (the group holding the option's first block)
 // writes the option's date constants and clears its barrier words; wave
 // blocks [w0, w1) are generated.
-template <typename T, int WHAT, bool MID>
+template <typename T, int WHAT, bool MID, typename Node>
 __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__restrict__ V,
-                                         const BridgeNode *__restrict__ sched,
+                                         const Node *__restrict__ sched,
                                          const uint32_t *__restrict__ shift, bool init, int64_t w0,
                                          int64_t w1)
 {
@@ -379,7 +385,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
 #pragma unroll
                 for (int q = 0; q < kTailChunk; ++q) {
                     if (s0 + q < M) {
-                        const BridgeNode &nd = sched[s0 + q];
+                        const Node &nd = sched[s0 + q];
                         const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
                         const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl),
                                   n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
@@ -407,7 +413,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             // the schedule through a loaded descriptor, and a window index the
             // compiler cannot prove uniform turns every slot access into a
             // compare-and-select chain
-            const BridgeNode &nd = sched[s];
+            const Node &nd = sched[s];
             const int j = __builtin_amdgcn_readfirstlane(nd.dim);
             const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
             const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl), n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
@@ -464,7 +470,7 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
     if (WHAT == 0)
         for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < a.rows_n; q += (int64_t)gridDim.x * kWG)
             a.rows[q] = 0ull;
-    gen_body<T, WHAT, MID>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
+    gen_body<T, WHAT, MID, BridgeNode>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
 }
 
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
@@ -615,14 +621,28 @@ gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ 
     const int64_t per = (u.b1 - u.b0 + kWaves - 1) / kWaves;
     const int64_t w0 = u.b0 + (int64_t)(threadIdx.x >> 6) * per;
     const int64_t w1 = min(w0 + per, u.b1);
-    gen_body<T, 0, false>(a, V, o.sched, nullptr, u.b0 == 0, w0, w1);
+    // the option's bridge schedule copied into LDS past gen_body's regions
+    // (read by gen_body after its first barrier): co-resident groups of
+    // different options would otherwise each walk their own schedule through
+    // the shared scalar cache, one miss per date
+    extern __shared__ uint32_t lds[];
+    LdsNode *nodes = reinterpret_cast<LdsNode *>(reinterpret_cast<char *>(lds) +
+                                                 (generate_lds_bytes(o.M, sizeof(T) == 8) + 15) / 16 * 16);
+    for (int q = threadIdx.x; q < o.M; q += kWG) {
+        const BridgeNode &b = o.sched[q];
+        LdsNode n;
+        n.dim = b.dim; n.m = b.m; n.sl = b.sl; n.sr = b.sr; n.dst = b.dst; n.pad = 0;
+        n.wl = b.wl; n.wr = b.wr; n.sd = b.sd;
+        nodes[q] = n;
+    }
+    gen_body<T, 0, false, LdsNode>(a, V, nodes, nullptr, u.b0 == 0, w0, w1);
 }
 
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
                                  hipStream_t s)
 {
-    const size_t lds = generate_lds_bytes(max_dates, fp64);
+    const size_t lds = (generate_lds_bytes(max_dates, fp64) + 15) / 16 * 16 + (size_t)max_dates * sizeof(LdsNode);
     if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
     else      hipLaunchKernelGGL((gen_batch_kernel<float>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
     return hipGetLastError();
