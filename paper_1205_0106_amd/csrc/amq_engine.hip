@@ -105,8 +105,8 @@ std::vector<amq::BridgeNode> make_schedule(int M)
         n.dim = dim_of[m];
         n.sl = sl; n.sr = sr; n.dst = dst;
         n.fm = (float)m;
-        if (l == 0 && r == 0) {           // root: W(t_M) = sqrt(M) z in sqrt(dt) units
-            n.wl = 0.0; n.wr = 0.0; n.sd = sqrt((double)M);
+        if (l == 0 && r == 0) {           // root: W(t_M) = anchor + sqrt(M) z in sqrt(dt) units
+            n.wl = 1.0; n.wr = 0.0; n.sd = sqrt((double)M);
         } else {
             const double span = (double)(r - l);
             n.wl = (double)(r - m) / span;
@@ -116,7 +116,7 @@ std::vector<amq::BridgeNode> make_schedule(int M)
         n.fwl = (float)n.wl; n.fwr = (float)n.wr; n.fsd = (float)n.sd;
         out.push_back(n);
     };
-    emit(M, 0, 0, 0, 0, 1);
+    emit(M, 0, 0, amq::kAnchorSlot, 0, 1);
     // explicit stack: (l, r, slot of W(l), slot of W(r), depth of the midpoint)
     struct Fr { int l, r, sl, sr, depth; };
     std::vector<Fr> st;
@@ -190,7 +190,7 @@ int get_schedule(DevState *st, int M, const amq::BridgeNode **out)
     auto it = st->sched.find(M);
     if (it != st->sched.end()) { *out = it->second; return AM_OK; }
     std::vector<amq::BridgeNode> h = make_schedule(M);
-    if ((int)h.size() != M || max_slot(h) >= amq::kMaxSlots)
+    if ((int)h.size() != M || max_slot(h) >= amq::kAnchorSlot)
         return fail(AM_EDIM, "bridge schedule for %d dates does not fit the register window", M);
     amq::BridgeNode *d = nullptr;
     const size_t b = sizeof(amq::BridgeNode) * (size_t)M;

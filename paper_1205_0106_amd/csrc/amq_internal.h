@@ -9,6 +9,7 @@ namespace amq {
 constexpr int kWG = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
 constexpr int kMaxSlots = 16;     // bridge register window (tree depth + 2; depth <= 10 for 640 dates)
+constexpr int kAnchorSlot = kMaxSlots - 1;   // read by the first bridge node only
 constexpr int kMaxDates = 640;    // on-chip Sobol lane tables (<= 64 KiB of LDS) bound this
 constexpr int kRec = 40;          // doubles per date record
 constexpr int kRecTime = 32;      // record slots 32..37: device clock stamps of the date's phases
@@ -42,7 +43,13 @@ constexpr int64_t kLdAlign = 32768;
 // value of W at date m (in units of sqrt(dt)) is
 //   W[dst] = wl * W[sl] + wr * W[sr] + sd * z(dim)
 // where slots hold the values of the current node's ancestors (slot 0 is the
-// constant W(0) = 0).  Both precisions are stored so each kernel reads one.
+// constant W(0) = 0).  The first node (date M) reads the anchor slot
+// kAnchorSlot with weight 1, which holds 0 for W; no node writes that slot.
+// Because wl + wr = 1 below the root, the same schedule carries any process
+// a + b t + c W(t): the generation kernels run it on the log-price
+// log S0 + (r - sigma^2/2) t + sigma W(t), with slot 0 = log S0, the anchor
+// = log S0 + (r - sigma^2/2) T and sigma sqrt(dt) z in place of z.
+// Both precisions are stored so each kernel reads one.
 struct alignas(64) BridgeNode {
     int32_t m;      // date index 1..M
     int32_t dim;    // Sobol dimension, 0-based

@@ -94,8 +94,10 @@ template <> struct MoroParts<double> {
     {
         const double y = ((double)x - 2147483648.0) * 0x1p-32;
         const double r = y * y;
-        const double num = y * (((AMQ_A3 * r + AMQ_A2) * r + AMQ_A1) * r + AMQ_A0);
-        const double den = (((AMQ_B3 * r + AMQ_B2) * r + AMQ_B1) * r + AMQ_B0) * r + 1.0;
+        // the fused steps the compiler forms from the plain expression, in
+        // the three-address form
+        const double num = y * fma3(fma3(fma3(AMQ_A3, r, AMQ_A2), r, AMQ_A1), r, AMQ_A0);
+        const double den = fma(fma3(fma3(fma3(AMQ_B3, r, AMQ_B2), r, AMQ_B1), r, AMQ_B0), r, 1.0);
         return num * rcp_f64(den);   // (a tail point's value is discarded)
     }
     static __device__ __forceinline__ double tail_value(uint32_t x)
@@ -320,8 +322,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     // binary32; the exercise decisions
     // downstream are sensitive to path-value errors well below a binary32 ulp,
     // so nothing but the final rounding is left in binary32).  Only the
-    // inverse normal is evaluated in the storage precision.
-    const double S0 = a.S0, mu = a.mu, vol = a.vol;
+    // inverse normal is evaluated in the storage precision.  The bridge runs
+    // on the log-price X(t_m) = log S0 + mu m + vol W(m) (the schedule's
+    // weights sum to 1, so interpolation carries the constant and the drift),
+    // and S = exp(X): no per-date drift, volatility or S0 products.
+    const double vol = a.vol;
     // Padding paths (past N) hold K rounded in the storage precision away
     // from the money, so h(S) <= 0 in binary64 and the sweep never counts
     // them in the money.
@@ -331,9 +336,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
         if (a.is_call && (double)Kp > a.K) Kp = nextafterf(Kp, -INFINITY);
     }
 
-    double W[kMaxSlots];
+    double X[kMaxSlots];
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) W[q] = 0.0;
+    for (int q = 0; q < kMaxSlots; ++q) X[q] = 0.0;
+    X[0] = log(a.S0);                                   // X(t_0)
+    X[kAnchorSlot] = X[0] + a.mu * (double)M;           // read by the root node only
 
     for (int64_t w = w0; w < w1; ++w) {
         const int64_t i = (w << 6) + lane;
@@ -394,10 +401,9 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                                      n_sd = uniform_f64(nd.sd);
                         const T zc = MoroParts<T>::central(xs[q]);
                         const T z = tl[q] ? tz[slot[q]] : zc;
-                        const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
-                        W[n_dst] = wv;
-                        const double e = mu * (double)n_m + vol * wv;
-                        const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp_poly(e)));
+                        const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * (double)z);
+                        X[n_dst] = xv;
+                        const T Sv = (T)(sizeof(T) == 4 ? exp_poly_f32(xv) : exp_poly<true>(xv));
                         ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
                     }
                 }
@@ -430,10 +436,9 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = (double)z;
                 continue;
             }
-            const double wv = n_wl * W[n_sl] + n_wr * W[n_sr] + n_sd * (double)z;
-            W[n_dst] = wv;
-            const double e = mu * (double)n_m + vol * wv;
-            const T Sv = (T)(S0 * (sizeof(T) == 4 ? exp_poly_f32(e) : exp_poly(e)));
+            const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * (double)z);
+            X[n_dst] = xv;
+            const T Sv = (T)(sizeof(T) == 4 ? exp_poly_f32(xv) : exp_poly<true>(xv));
             ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {

@@ -5,26 +5,43 @@
 
 namespace amq {
 
+// p*g + c rounded once (v_fma_f64), with c in a register of its own.  The
+// compiler's selection of a polynomial step with a loop-invariant, non-inline
+// coefficient is the two-address v_fmac_f64 plus a v_mov_b64 that copies the
+// coefficient into the accumulator first: one extra vector instruction per
+// step.  The three-address form needs no copy; the result is the same fma.
+__device__ __forceinline__ double fma3(double p, double g, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(g), "v"(c));
+    return r;
+}
+
 // exp(x) in binary64: n = rint(x log2(e)), g = x - n ln 2 (Cody-Waite: ln 2
 // split into a 53-bit head and its tail, each product taken exactly inside
 // an fma), |g| <= 0.3466; exp(x) = 2^n e^g with e^g from its Taylor series to
 // degree 12 (truncation below 0.3466^13 / 13! < 2e-16 relative).  Intended
 // for the arguments the kernels produce (|x| < 700); very negative x
-// underflows to 0 through ldexp.
+// underflows to 0 through ldexp.  kFma3 evaluates the polynomial with fma3
+// (same values): it pays where the coefficients stay in vector registers
+// across a loop, as in path generation; elsewhere the compiler's own form is
+// kept.
+template <bool kFma3 = false>
 __device__ __forceinline__ double exp_poly(double x)
 {
+    const auto step = [](double p, double g, double c) { return kFma3 ? fma3(p, g, c) : fma(p, g, c); };
     const double n = rint(x * 1.4426950408889634);
     const double g = fma(-n, 2.3190468138462996e-17, fma(-n, 0.69314718055994529, x));
     double p = 1.0 / 479001600.0;                  // 1/12!
-    p = fma(p, g, 1.0 / 39916800.0);               // 1/11!
-    p = fma(p, g, 1.0 / 3628800.0);
-    p = fma(p, g, 1.0 / 362880.0);
-    p = fma(p, g, 1.0 / 40320.0);
-    p = fma(p, g, 1.0 / 5040.0);
-    p = fma(p, g, 1.0 / 720.0);
-    p = fma(p, g, 1.0 / 120.0);
-    p = fma(p, g, 1.0 / 24.0);
-    p = fma(p, g, 1.0 / 6.0);
+    p = step(p, g, 1.0 / 39916800.0);               // 1/11!
+    p = step(p, g, 1.0 / 3628800.0);
+    p = step(p, g, 1.0 / 362880.0);
+    p = step(p, g, 1.0 / 40320.0);
+    p = step(p, g, 1.0 / 5040.0);
+    p = step(p, g, 1.0 / 720.0);
+    p = step(p, g, 1.0 / 120.0);
+    p = step(p, g, 1.0 / 24.0);
+    p = step(p, g, 1.0 / 6.0);
     p = fma(p, g, 0.5);
     p = fma(p, g, 1.0);
     p = fma(p, g, 1.0);
@@ -39,11 +56,11 @@ __device__ __forceinline__ double exp_poly_f32(double x)
     const double n = rint(x * 1.4426950408889634);
     const double g = fma(-n, 2.3190468138462996e-17, fma(-n, 0.69314718055994529, x));
     double p = 1.0 / 40320.0;                      // 1/8!
-    p = fma(p, g, 1.0 / 5040.0);
-    p = fma(p, g, 1.0 / 720.0);
-    p = fma(p, g, 1.0 / 120.0);
-    p = fma(p, g, 1.0 / 24.0);
-    p = fma(p, g, 1.0 / 6.0);
+    p = fma3(p, g, 1.0 / 5040.0);
+    p = fma3(p, g, 1.0 / 720.0);
+    p = fma3(p, g, 1.0 / 120.0);
+    p = fma3(p, g, 1.0 / 24.0);
+    p = fma3(p, g, 1.0 / 6.0);
     p = fma(p, g, 0.5);
     p = fma(p, g, 1.0);
     p = fma(p, g, 1.0);
