@@ -67,10 +67,15 @@ __device__ __forceinline__ void solve_date(const double *tot, double *beta, doub
     beta[9] = n;
 }
 
-// Laguerre weight exp(-x/2) with x = S/K (wc = -1/(2K)), binary64.
+// Laguerre weight exp(-x/2) with x = S/K (wc = -1/(2K)), binary64.  With
+// binary32 path values the degree-8 exponential (2.1e-10 relative) serves:
+// the stored values themselves are 3e-8 away from the binary64 paths, and
+// every use of a path's weight (both moment sums and the continuation value)
+// reads this same value.
+template <typename T>
 __device__ __forceinline__ double lag_weight(double s, double wc)
 {
-    return exp_poly(s * wc);
+    return sizeof(T) == 4 ? exp_poly_f32(s * wc) : exp_poly(s * wc);
 }
 
 // 16-byte vector of path values: 4 binary32 or 2 binary64 consecutive paths.
@@ -129,14 +134,14 @@ __device__ __forceinline__ double payoff_arg(double s, double sg, double nsk)
 // Adds path value s (cashflow pvj discounted to t0) to the in-the-money
 // moments acc[0..NA-1] (sum of wA xs^q) and acc[NA..NA+NB-1] (sum of wB xs^q
 // pvj); returns 1 if the path is in the money.  (Streamed tiles: one pass.)
-template <int D, bool LAG, bool PIN = true>
+template <typename T, int D, bool LAG, bool PIN = true>
 __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, double sg, double nsk, double xa,
                                            double xb, double wc)
 {
     constexpr int NA = 2 * D + 1, NB = D + 1;
     const bool itm = payoff_arg(s, sg, nsk) > 0.0;
     const double xs = fma(s, xa, xb);
-    const double w = LAG ? lag_weight(s, wc) : 1.0;
+    const double w = LAG ? lag_weight<T>(s, wc) : 1.0;
     // y_q = w xs^q on an in-the-money path (0 otherwise): the Gram moments
     // are sum w y_q (w = 1: sum y_q) and the right-hand side sum pvj y_q, so
     // one product chain serves both
@@ -162,7 +167,7 @@ __device__ __forceinline__ int moments_add(double *acc, double s, double pvj, do
 // right-hand side (sum of wB xs^q pvj), with the same product chain, so each
 // sum is bitwise the one moments_add forms.  gram_add stores the Laguerre
 // weight for rhs_add and the exercise update.
-template <int D, bool LAG>
+template <typename T, int D, bool LAG>
 __device__ __forceinline__ bool gram_add(double *acc, double s, double sg, double nsk, double xa, double xb,
                                          double wc, double *wout, double *yout = nullptr)
 {
@@ -171,7 +176,7 @@ __device__ __forceinline__ bool gram_add(double *acc, double s, double sg, doubl
     const double xs = fma(s, xa, xb);
     double w = 1.0;
     if (LAG) {
-        w = lag_weight(s, wc);
+        w = lag_weight<T>(s, wc);
         *wout = w;
     }
     double y = itm ? w : 0.0;
@@ -218,7 +223,7 @@ __device__ __forceinline__ T exercise_update(T s_t, T pvj, double sg, double nsk
     double cont = gam[P - 1];
 #pragma unroll
     for (int q = P - 2; q >= 0; --q) cont = fma(cont, xs, gam[q]);
-    if (LAG) cont *= wgiven ? *wgiven : lag_weight(s, wc);
+    if (LAG) cont *= wgiven ? *wgiven : lag_weight<T>(s, wc);
     const double ex = dk * h;
     // in the money and above the continuation: with dk > 0, ex > 0 exactly
     // when h > 0 (|h| is at least an ulp of K, far from underflow), so this
@@ -391,9 +396,9 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
 #pragma unroll
             for (int e = 0; e < VW; e += 2) {
                 const int j0 = jj * VW + e;
-                const bool i0 = gram_add<D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * WG,
+                const bool i0 = gram_add<T, D, LAG>(g, (double)v[jj].v[e], sg, nsk, xa, xb, wc, wl + j0 * WG,
                                                  kCacheY ? ys[kCacheY ? j0 : 0] : nullptr);
-                const bool i1 = gram_add<D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc,
+                const bool i1 = gram_add<T, D, LAG>(g2, (double)v[jj].v[e + 1], sg, nsk, xa, xb, wc,
                                                  wl + (j0 + 1) * WG, kCacheY ? ys[kCacheY ? j0 + 1 : 0] : nullptr);
                 cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i0)) +
                        (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(i1));
@@ -586,7 +591,7 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
                 if (jj < NK) s_keep[jj * WG + tid] = cur;   // the update reads these back
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
-                    cnt += moments_add<D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], sg, nsk, xa, xb, wc);
+                    cnt += moments_add<T, D, LAG>(acc, (double)cur.v[e], (double)pv[jj * VW + e], sg, nsk, xa, xb, wc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
