@@ -59,6 +59,38 @@ def measured_traffic(config: int, dtype: str, kernel: str):
     return None if k is None else k["traffic_bytes"]
 
 
+PEAK_VALU_LANE_PER_S = 256 * 4 * 16 * 2.4e9   # 1024 SIMDs x 16 lanes x 2.4 GHz (binary64 FMA at full rate)
+
+
+def measured_valu(config: int, dtype: str, kernel: str):
+    """Wave-level vector instructions per launch of `kernel` from the committed
+    rocprofv3 counter runs (SQ_INSTS_VALU), or None when those runs were taken
+    on other kernel sources, dtype or workload."""
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if dtype != "fp32" or not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t["kernels"].get(f"cfg{config}:{'sweep_kernel' if kernel == 'sweep' else 'gen_kernel'}")
+    return None if k is None else k["valu_wave_instr"]
+
+
+def valu_issue(config: int, dtype: str, phase_ms: dict):
+    """Vector-instruction issue rate of both kernels against the SIMDs' peak:
+    counted instructions (profiles) over the launch times measured here."""
+    out = {}
+    for kernel in ("generate", "sweep"):
+        n = measured_valu(config, dtype, kernel)
+        if n is None:
+            continue
+        achieved = n * 64 / (phase_ms[kernel] * 1e-3)
+        out[kernel] = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                       "peak": round(PEAK_VALU_LANE_PER_S / 1e12, 3), "unit": "T lane-instr/s",
+                       "frac": round(achieved / PEAK_VALU_LANE_PER_S, 4), "valu_wave_instr_per_launch": n}
+    return out or None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +327,7 @@ def main():
                    if dtype == "fp32" else "FP64 throughout",
                    "S0": w.S0, "K": w.K, "r": w.r, "sigma": w.sigma, "T": w.T},
         "roofline": roofline,
+        "valu_issue": valu_issue(args.config, dtype, {"generate": m["gen_ms"], "sweep": m["sweep_ms"]}),
         "phase_ms": {"generate": round(m["gen_ms"], 4), "sweep": round(m["sweep_ms"], 4)},
         "price": m["price"],
         "std_err": m["std_err"],
