@@ -103,6 +103,21 @@ def test_schedule_gives_brownian_covariance(amq, M):
     assert np.abs(cov - np.minimum.outer(t, t)).max() < 1e-9 * M
 
 
+@pytest.mark.parametrize("M", [1, 2, 7, 100, 252, 640])
+def test_schedule_weights_carry_drift(amq, M):
+    # the kernels run the schedule on the log-price a + b t + c W(t): below the
+    # root the two interpolation weights must sum to 1 and reproduce the
+    # linear drift exactly (b m = wl b l + wr b r); the root reads its anchor
+    # (log S0 + b M) with weight 1
+    sc = amq.am_debug_schedule(M)
+    assert sc["wl"][0] == 1.0 and sc["wr"][0] == 0.0 and sc["m"][0] == M
+    for q in range(1, M):
+        wl, wr = sc["wl"][q], sc["wr"][q]
+        l, r, m = sc["left"][q], sc["right"][q], sc["m"][q]
+        assert abs(wl + wr - 1.0) <= 2.3e-16
+        assert abs(wl * l + wr * r - m) <= 1e-12 * M
+
+
 @pytest.mark.parametrize("M", [1, 5, 50, 365])
 def test_schedule_dimension_numbering_is_breadth_first(amq, orc, M):
     # each date must read the same Sobol dimension as in the breadth-first
