@@ -155,6 +155,13 @@ struct DevState {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     std::map<long, int> occ;                        // (kind, fp64, wg, ppt, degree) -> groups per CU
+    // single-option sweeps hold every CU for their whole run and wait on one
+    // another's groups only within their own grid: launches on different
+    // streams are ordered through this event, in enqueue order, so two never
+    // share the device
+    std::mutex persist_mu;
+    hipEvent_t persist_done = nullptr;
+    hipStream_t persist_stream = nullptr;
 };
 
 std::mutex g_dev_mu;
@@ -366,7 +373,19 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     sa.rep_out = rep >= 0 ? (double *)(ws + L.off_rep) : nullptr;
     sa.rep = rep;
     sa.n_rep = n_rep;
-    hipError_t e = amq::launch_sweep(sa, fp64, plan.wg, plan.ppt, stream);
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> lk(st->persist_mu);
+        if (!st->persist_done)
+            HIP_TRY(hipEventCreateWithFlags(&st->persist_done, hipEventDisableTiming));
+        else if (st->persist_stream != stream)
+            HIP_TRY(hipStreamWaitEvent(stream, st->persist_done, 0));
+        e = amq::launch_sweep(sa, fp64, plan.wg, plan.ppt, stream);
+        if (e == hipSuccess) {
+            HIP_TRY(hipEventRecord(st->persist_done, stream));
+            st->persist_stream = stream;
+        }
+    }
     if (e != hipSuccess)
         return fail(AM_EDEVICE, "sweep launch (%d threads, ppt %d, groups %d) failed: %s", plan.wg, plan.ppt, plan.G,
                     hipGetErrorString(e));
