@@ -26,6 +26,12 @@ __device__ __forceinline__ double fma3(double p, double g, double c)
 // (same values): it pays where the coefficients stay in vector registers
 // across a loop, as in path generation; elsewhere the compiler's own form is
 // kept.
+// 1/4! and 1/8! one ulp above their nearest binary64 values (7e-18 and 3e-21
+// higher, far below either polynomial's truncation): rounded to nearest, each
+// shares its low 32 bits with 1/3! or 1/7!, and the compiler then keeps one
+// register for both low words and copies it into place inside the loop.
+constexpr double kInvFact4 = 0x1.5555555555556p-5, kInvFact8 = 0x1.a01a01a01a01bp-16;
+
 template <bool kFma3 = false>
 __device__ __forceinline__ double exp_poly(double x)
 {
@@ -36,11 +42,11 @@ __device__ __forceinline__ double exp_poly(double x)
     p = step(p, g, 1.0 / 39916800.0);               // 1/11!
     p = step(p, g, 1.0 / 3628800.0);
     p = step(p, g, 1.0 / 362880.0);
-    p = step(p, g, 1.0 / 40320.0);
+    p = step(p, g, kInvFact8);
     p = step(p, g, 1.0 / 5040.0);
     p = step(p, g, 1.0 / 720.0);
     p = step(p, g, 1.0 / 120.0);
-    p = step(p, g, 1.0 / 24.0);
+    p = step(p, g, kInvFact4);
     p = step(p, g, 1.0 / 6.0);
     p = fma(p, g, 0.5);
     p = fma(p, g, 1.0);
@@ -55,11 +61,11 @@ __device__ __forceinline__ double exp_poly_f32(double x)
 {
     const double n = rint(x * 1.4426950408889634);
     const double g = fma(-n, 2.3190468138462996e-17, fma(-n, 0.69314718055994529, x));
-    double p = 1.0 / 40320.0;                      // 1/8!
+    double p = kInvFact8;
     p = fma3(p, g, 1.0 / 5040.0);
     p = fma3(p, g, 1.0 / 720.0);
     p = fma3(p, g, 1.0 / 120.0);
-    p = fma3(p, g, 1.0 / 24.0);
+    p = fma3(p, g, kInvFact4);
     p = fma3(p, g, 1.0 / 6.0);
     p = fma(p, g, 0.5);
     p = fma(p, g, 1.0);
