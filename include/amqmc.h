@@ -109,7 +109,11 @@ int am_workspace_layout(int64_t n_paths, int32_t n_dates, am_basis basis, int32_
 /* Price one option asynchronously on `hip_stream` (a hipStream_t; NULL is the
  * null stream) using the caller's device workspace d_workspace of ws_bytes
  * (>= am_workspace_bytes, 256-byte aligned, on the current device).  The
- * workspace must not be shared by calls that may overlap.  If h_out is
+ * workspace must not be shared by calls that may overlap.  Calls enqueued
+ * on different streams of one device may overlap in generation; their
+ * sweeps (each holding every CU) run one after another, in enqueue order.
+ * A sweep kept from being fully resident by other work on the device waits
+ * boundedly and then fails with AM_ETIMEOUT.  If h_out is
  * non-NULL the call waits for the stream and writes h_out[0] = price,
  * h_out[1] = std_err; if NULL it returns after enqueueing and the result
  * stays in the workspace result region. */
