@@ -104,6 +104,10 @@ def parse():
                     help="serving mode: replay Poisson arrivals (200 req/s) for SECONDS")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="batch mode: price N options of the seeded batch workload in one call")
+    ap.add_argument("--paper-estimator", action="store_true",
+                    help="the paper's eqs. (10)-(11) estimator on the workload's paths and dates")
+    ap.add_argument("--rqmc", type=int, default=0, metavar="R",
+                    help="randomised QMC: R digitally shifted replicates of N/R paths each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -233,6 +237,46 @@ def batch_run(n, dtype, steps, warmup):
             "phase_ms": {"generate": gen_ms / calls, "sweep": sweep_ms / calls}}
 
 
+def variant_run(args):
+    """The paper's own estimator, or randomised QMC, on the workload's option,
+    dates and total path count; whole-call wall time between device syncs."""
+    import numpy as np
+    import torch
+    import paper_1205_0106_amd as amq
+    from paper_1205_0106_amd.workloads import CONFIGS
+    w = CONFIGS[args.config]
+    dtype = args.dtype or ("fp32" if "fp32" in w.dtypes else "fp64")
+    p = amq.make_params(**w.params(), is_call=w.is_call, allow_exercise=w.allow_exercise)
+    pr = amq.Pricer(0)
+    if args.paper_estimator:
+        call = lambda wait: pr.price_paper(p, w.n_paths, w.n_dates, dtype, wait=wait)
+        n_paths, what = w.n_paths, "the paper's estimator (eqs. (10)-(11)): Black-Scholes last interval, pathwise maximum"
+    else:
+        R = args.rqmc
+        n_paths = w.n_paths // R
+        b = amq.make_basis(*w.basis)
+        shifts = np.random.default_rng(20120501).integers(0, 2 ** 32, size=(R, w.n_dates), dtype=np.uint32)
+        call = lambda wait: pr.price_rqmc(p, n_paths, w.n_dates, b, dtype, shifts)
+        what = f"randomised QMC: {R} digitally shifted replicates of {n_paths} paths, {w.basis[0]} degree {w.basis[1]}"
+    for _ in range(args.warmup):
+        call(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = call(False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = call(True)
+    total = (n_paths * (args.rqmc or 1)) * w.n_dates
+    return {"metric": "path-steps/s for QMC American pricing (" + ("paper estimator" if args.paper_estimator
+                                                                   else "randomised QMC-LSM") + ")",
+            "value": total * args.steps / dt, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+            "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64", "data": "synthetic (on-device Sobol paths)",
+            "config": {"workload": w.name, "variant": what, "path_steps": total},
+            "price": float(res[0]), "error_bar": float(res[1])}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -275,6 +319,9 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_run(args.batch, args.dtype or "fp32", args.steps, args.warmup)), flush=True)
+        return
+    if args.paper_estimator or args.rqmc:
+        print(json.dumps(variant_run(args)), flush=True)
         return
     import torch
     import paper_1205_0106_amd as amq
