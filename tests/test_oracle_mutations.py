@@ -63,6 +63,13 @@ MUTANTS = [
      "z[q] = shift ? or_inv_normal_mid_u32(or_sobol_int(V, q, n))"),
     ("midpoint offset dropped", "double y = ((double)x + 0.5 - 2147483648.0) * s;",
      "double y = ((double)x - 2147483648.0) * s;"),
+    ("paper final discount dropped", "c[i] = disc * v;", "c[i] = v;"),
+    ("paper last interval over T", "or_bs_price(S, p->K, p->r, p->sigma, dt, p->is_call)",
+     "or_bs_price(S, p->K, p->r, p->sigma, p->T, p->is_call)"),
+    ("paper backward discount dropped", ": disc * v;", ": v;"),
+    ("paper grid spacing T/m", "double dt = p->T / (double)(m + 1);", "double dt = p->T / (double)m;"),
+    ("paper pathwise maximum dropped", "v = h > cont ? h : cont;", "v = cont;"),
+    ("paper horizon is T", "double horizon = dt * (double)m;", "double horizon = p->T;"),
     ("crr bermudan stride", "int ex = (style == OR_AMERICAN) || (style == OR_BERMUDAN && i % stride == 0);",
      "int ex = (style == OR_AMERICAN) || (style == OR_BERMUDAN && i % stride == 1);"),
 ]
@@ -99,6 +106,9 @@ def _pin_suite(orc):
         lambda: P.test_config1_lsm_close_to_bermudan_tree(orc),
         lambda: P.test_midpoint_inverse_normal(orc),
         lambda: P.test_rqmc_exercise_off_covers_black_scholes(orc),
+        lambda: P.test_paper_estimator_no_dates_is_black_scholes(orc),
+        lambda: P.test_paper_estimator_deterministic_paths(orc, 3),
+        lambda: P.test_paper_estimator_one_point_call_is_black_scholes(orc, P.CONFIG2),
     ]
 
 

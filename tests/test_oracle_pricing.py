@@ -232,6 +232,38 @@ def test_paper_estimator_is_an_upper_bound(orc):
     assert up.price > lsm.price
 
 
+@pytest.mark.parametrize("m", [1, 3, 10])
+def test_paper_estimator_deterministic_paths(orc, m):
+    # sigma -> 0 makes every path deterministic, S_t = S0 e^{rt}, and eq. (10)'s
+    # Black-Scholes value over the last interval dt = T/(m+1) becomes
+    # max(S - K e^{-r dt}, 0) for a call, max(K e^{-r dt} - S, 0) for a put.
+    # In-the-money call (r > 0): holding beats exercise at every point
+    # (S_i - K < e^{-r dt} c_{i+1} = S_i - K e^{-r(m-i+1)dt}), so the value
+    # discounted to t0 is S0 - K e^{-rT}.  In-the-money put: exercise at t_1
+    # wins (K - S_1 > K e^{-r dt} - S_1), worth K e^{-r dt} - S0 at t0.  A
+    # dropped discount in eq. (11) or in the final step, or the last interval
+    # taken over T, moves both values by far more than the tolerance.
+    r, T = 0.05, 1.0
+    dt = T / (m + 1)
+    call = orc.paper_estimator(S0=120.0, K=100.0, r=r, sigma=1e-9, T=T, N=1024, m=m, is_call=True)
+    assert abs(call.price - (120.0 - 100.0 * math.exp(-r * T))) < 1e-8
+    put = orc.paper_estimator(S0=80.0, K=100.0, r=r, sigma=1e-9, T=T, N=1024, m=m, is_call=False)
+    assert abs(put.price - (100.0 * math.exp(-r * dt) - 80.0)) < 1e-8
+
+
+@pytest.mark.parametrize("cfg", [CONFIG1, CONFIG2, CONFIG4])
+def test_paper_estimator_one_point_call_is_black_scholes(orc, cfg):
+    # m = 1: one point at t_1 = T/2 with dt = T/2.  For a call with r >= 0 the
+    # Black-Scholes value over dt is at least S - K e^{-r dt} >= h(S), so the
+    # pathwise maximum of eq. (10) is the Black-Scholes value itself, and by the
+    # tower property e^{-r dt} E[BS(S_dt, dt)] = BS(S0, 2 dt) = BS(S0, T).  The
+    # quasi-random mean over Sobol dimension 1 is a 1-D quadrature of a smooth
+    # function, within 2K/N of the integral at N = 2^14 (measured about 0.8K/N).
+    N = 1 << 14
+    got = orc.paper_estimator(**cfg, N=N, m=1, is_call=True)
+    assert abs(got.price - orc.bs_price(**cfg, is_call=True)) < 2.0 * cfg["K"] / N
+
+
 # --------------------------------------------------------------------------
 # Randomised QMC (digital shifts, midpoint mapping)
 # --------------------------------------------------------------------------
