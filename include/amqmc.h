@@ -66,6 +66,21 @@ enum { AM_MAX_DEGREE = 6 };
  *                 perturbations near 1e-8 for some options). */
 enum { AM_FP64 = 0, AM_FP32_BULK = 1 };
 
+/* Storage rule for small requests.  With fewer than AM_FP32_MIN_PATHS paths a
+ * single exercise decision that rounds the other way in binary32 storage
+ * moves the price by up to (largest payoff)/N, which alone can exceed the
+ * FP32-bulk tolerance of 2e-3 absolute.  AM_FP32_BULK requests below that
+ * path count are therefore stored in binary64 (they are latency-bound, so the
+ * doubled bytes cost nothing measurable); every pricing entry point applies
+ * the rule (single option, randomised QMC per replicate, each option of a
+ * batch, each served request), workspace sizes and layouts included.  The
+ * paper's estimator (no regression, no decision feedback) stores as asked. */
+enum { AM_FP32_MIN_PATHS = 16384 };
+
+/* The storage type (AM_FP64 or AM_FP32_BULK) a pricing request of n_paths
+ * paths gets under that rule; -1 for an unknown dtype. */
+int32_t am_storage_dtype(int64_t n_paths, int32_t dtype);
+
 enum {
     AM_OK = 0,
     AM_EINVAL = -1,      /* a parameter is out of range or not finite */
@@ -88,7 +103,8 @@ size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int3
 
 /* Offsets (bytes from the workspace base) of the regions a test or tool may
  * read after a call, in this order:
- *   [0] S: paths, [n_dates][ld] of double (AM_FP64) or float (AM_FP32_BULK),
+ *   [0] S: paths, [n_dates][ld] of double or float, as am_storage_dtype()
+ *       names for (n_paths, dtype),
  *       row k-1 holds t_k, column i holds path i;
  *   [1] PV: [ld] per-path cashflow discounted to t0, same type as S;
  *   [2] per-date records: [n_dates+1][40] double; row k (1 <= k < n_dates)
@@ -170,10 +186,13 @@ size_t am_batch_workspace_bytes(const am_option *opts, int32_t n_opts, am_basis 
  * persistent launch in which workgroups claim (option, tile) slots and each
  * option synchronises only its own tiles, so options of uneven path and date
  * counts overlap on the device.  Each option's result depends only on its own
- * data (fixed-order reductions): the same alone and in any mix.  h_out
- * (2 * n_opts doubles, or NULL to return after enqueueing) receives price
- * and std_err per option in the caller's order.  Fails with AM_EDIM if one
- * option needs more tiles than the device holds resident. */
+ * data (fixed-order reductions): the same alone and in any mix.  Under
+ * AM_FP32_BULK, options below AM_FP32_MIN_PATHS paths form a second
+ * sub-batch stored in binary64 (a second generation and sweep launch on the
+ * stream; am_batch_workspace_bytes covers both).  h_out (2 * n_opts
+ * doubles, or NULL to return after enqueueing) receives price and std_err
+ * per option in the caller's order.  Fails with AM_EDIM if one option needs
+ * more tiles than the device holds resident. */
 int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
                    void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out);
 
@@ -272,12 +291,18 @@ typedef struct am_result {
  * the free pool (and under the batch caps) is launched as one batch
  * (am_price_batch's kernels, persistent grid limited to 1/n_streams of the
  * device so in-flight batches run side by side); completed batches return
- * their memory.  Paths and cashflows stay resident in the pool until a
+ * their memory.  A request whose sweep needs more workgroups than that share
+ * runs alone on the whole device once every stream is idle (later requests
+ * wait behind it).  Paths and cashflows stay resident in the pool until a
  * request completes.  Results are those of am_price_batch, hence identical
- * to pricing the request alone. */
+ * to pricing the request alone.  The batch tile is the default one (FP32
+ * bulk 16 paths per thread, FP64 8), whatever am_batch_autotune chose. */
 int am_server_create(const am_server_config *cfg, am_server **out);
 
-/* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now. */
+/* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now.
+ * Returns AM_EDIM (and queues nothing) for a request whose sweep would not
+ * be resident even on the whole device; a request larger than the HBM
+ * budget is queued and completes with status AM_ENOMEM. */
 int am_server_submit(am_server *server, const am_option *opt, uint64_t request_id, double t_arrival);
 
 /* Move up to max_out completed results into out; *n_out receives the count. */
@@ -292,6 +317,17 @@ int am_server_stats(am_server *server, double out[4]);
 /* Finish every queued request, stop the dispatcher, free the pool.  Results
  * not yet polled are discarded.  Returns the first fatal error, if any. */
 int am_server_destroy(am_server *server);
+
+/* Release what the library holds for the life of the process: per device
+ * the direction-number table, the bridge schedules, the synchronous entry
+ * point's workspace and stream and the event that orders single-option
+ * sweeps; the pinned result buffers and profiling events of every thread.
+ * Waits for the library's own streams first.  Call it with no other library
+ * call in flight and no server alive (AM_EINVAL otherwise); a later call
+ * sets the state up again.  The Python binding calls it at interpreter exit,
+ * so nothing of the library is left for the HIP runtime (and a profiler
+ * attached to it) to tear down after its own finalisation. */
+int am_shutdown(void);
 
 /* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 4
  * or 16, FP64: 2 or 8; 0 restores the default).  Results of one option are

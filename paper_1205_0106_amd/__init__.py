@@ -11,6 +11,7 @@ Carlo Simulation for Pricing American Options" (Sections III.D, III.E, V).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -23,6 +24,7 @@ AM_OK, AM_EINVAL, AM_ENOMEM, AM_EDEVICE, AM_EDIM, AM_EWORKSPACE, AM_ETIMEOUT = 0
 AM_BASIS_MONOMIAL, AM_BASIS_LAGUERRE = 0, 1
 AM_FP64, AM_FP32_BULK = 0, 1
 AM_MAX_DEGREE = 6
+AM_FP32_MIN_PATHS = 16384   # FP32-bulk requests below this path count are stored in binary64
 REC = 40            # doubles per per-date record in the workspace
 
 _BASIS_NAMES = {"monomial": AM_BASIS_MONOMIAL, "laguerre": AM_BASIS_LAGUERRE}
@@ -94,6 +96,10 @@ def lib():
                               "(or python -m paper_1205_0106_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
+        L.am_storage_dtype.argtypes = [ctypes.c_int64, ctypes.c_int32]
+        L.am_storage_dtype.restype = ctypes.c_int32
+        L.am_shutdown.argtypes = []
+        L.am_shutdown.restype = ctypes.c_int
         i64, i32, sz, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
         L.am_price_american.argtypes = [P(am_params), i64, i32, am_basis, i32, P(dbl), P(dbl)]
         L.am_price_american.restype = ctypes.c_int
@@ -161,7 +167,26 @@ def lib():
         L.am_debug_set_spin_limit.argtypes = [ctypes.c_uint32]
         L.am_debug_set_spin_limit.restype = None
         _lib = L
+        # release the library's process-lifetime HIP objects before the
+        # runtime (and any profiler attached to it) finalises
+        atexit.register(_shutdown_at_exit)
     return _lib
+
+
+def _shutdown_at_exit():
+    if _lib is not None:
+        _lib.am_shutdown()
+
+
+def am_shutdown() -> None:
+    """Release the library's process-lifetime device objects (it sets them up
+    again on the next call)."""
+    _check(lib().am_shutdown())
+
+
+def am_storage_dtype(n_paths: int, dtype) -> int:
+    """Storage type (AM_FP64 or AM_FP32_BULK) a pricing request gets."""
+    return int(lib().am_storage_dtype(int(n_paths), _dtype(dtype)))
 
 
 def _check(rc: int):
@@ -484,7 +509,7 @@ class Pricer:
         import torch
         lay = am_workspace_layout(n_paths, n_dates, basis, dtype)
         ws = self.ws
-        el = torch.float64 if _dtype(dtype) == AM_FP64 else torch.float32
+        el = torch.float64 if am_storage_dtype(n_paths, dtype) == AM_FP64 else torch.float32
         sz = 8 if el == torch.float64 else 4
         S = ws[lay.off_S: lay.off_S + n_dates * lay.ld * sz].view(el).view(n_dates, lay.ld)
         PV = ws[lay.off_PV: lay.off_PV + lay.ld * sz].view(el)

@@ -29,6 +29,13 @@ extern "C" const uint32_t amq_sobol_v32_dims;
 namespace {
 
 thread_local std::string g_err = "no error";
+// am_shutdown releases every thread's cached pinned buffer and profiling
+// events; a thread notices through the generation and sets them up again.
+std::mutex g_res_mu;
+uint64_t g_generation = 1;
+std::vector<void *> g_pinned_all;       // every thread's pinned result buffer
+std::vector<hipEvent_t> g_events_all;   // every thread's profiling events
+int g_live_servers = 0;
 thread_local uint32_t g_spin_limit = 0;
 thread_local int32_t g_batch_ppt = 0;   // batch tile choice (0 = default or tuned)
 constexpr uint32_t kDefaultSpin = 1u << 22;
@@ -53,6 +60,14 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Storage a pricing request gets: binary32 bulk storage only from
+// AM_FP32_MIN_PATHS paths up (below that one decision that rounds the other
+// way can exceed the FP32-bulk tolerance by itself).
+int32_t storage_of(int64_t N, int32_t dtype)
+{
+    return (dtype == AM_FP32_BULK && N < AM_FP32_MIN_PATHS) ? AM_FP64 : dtype;
+}
 
 struct Layout {
     int64_t ld;
@@ -297,14 +312,27 @@ struct Profiler {
     bool on = false;
     std::vector<ProfRec> pool;   // created events, reused
     size_t used = 0;
+    uint64_t gen = 0;            // g_generation the pool belongs to
 };
 thread_local Profiler g_prof;
 
 int prof_slot(ProfRec **out)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        if (g_prof.gen != g_generation) {   // released by am_shutdown
+            g_prof.pool.clear();
+            g_prof.used = 0;
+            g_prof.gen = g_generation;
+        }
+    }
     if (g_prof.used == g_prof.pool.size()) {
         ProfRec r;
-        for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&r.e[i]));
+        for (int i = 0; i < 3; ++i) {
+            HIP_TRY(hipEventCreate(&r.e[i]));
+            std::lock_guard<std::mutex> lk(g_res_mu);
+            g_events_all.push_back(r.e[i]);
+        }
         g_prof.pool.push_back(r);
     }
     *out = &g_prof.pool[g_prof.used++];
@@ -394,14 +422,24 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
 }
 
 thread_local double *g_pinned = nullptr;
+thread_local uint64_t g_pinned_gen = 0;
 
 int fetch_result(char *ws, const Layout &L, hipStream_t stream, double *h_out)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        if (g_pinned_gen != g_generation) {   // released by am_shutdown
+            g_pinned = nullptr;
+            g_pinned_gen = g_generation;
+        }
+    }
     if (!g_pinned) {
         if (hipHostMalloc((void **)&g_pinned, 256, hipHostMallocDefault) != hipSuccess) {
             g_pinned = nullptr;
             return fail(AM_ENOMEM, "hipHostMalloc of the result buffer failed");
         }
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        g_pinned_all.push_back(g_pinned);
     }
     HIP_TRY(hipMemcpyAsync(g_pinned, ws + L.off_result, 128, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -446,11 +484,17 @@ int64_t am_max_paths(int32_t dtype)
     return best;
 }
 
+int32_t am_storage_dtype(int64_t n_paths, int32_t dtype)
+{
+    if (dtype != AM_FP64 && dtype != AM_FP32_BULK) return -1;
+    return storage_of(n_paths, dtype);
+}
+
 size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype)
 {
     (void)basis;
     if (n_paths < 1 || n_dates < 1) return 0;
-    return make_layout(n_paths, n_dates, dtype).total;
+    return make_layout(n_paths, n_dates, storage_of(n_paths, dtype)).total;
 }
 
 int am_workspace_layout(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype, size_t out[6])
@@ -458,7 +502,7 @@ int am_workspace_layout(int64_t n_paths, int32_t n_dates, am_basis basis, int32_
     (void)basis;
     if (!out || n_paths < 1 || n_dates < 1 || (dtype != AM_FP64 && dtype != AM_FP32_BULK))
         return fail(AM_EINVAL, "bad arguments to am_workspace_layout");
-    Layout L = make_layout(n_paths, n_dates, dtype);
+    Layout L = make_layout(n_paths, n_dates, storage_of(n_paths, dtype));
     out[0] = L.off_S; out[1] = L.off_PV; out[2] = L.off_rec; out[3] = L.off_result;
     out[4] = (size_t)L.ld; out[5] = L.total;
     return AM_OK;
@@ -470,6 +514,7 @@ int am_price_american_ex(const am_params *params, int64_t n_paths, int32_t n_dat
 {
     int rc = validate(params, n_paths, n_dates, basis, dtype);
     if (rc) return rc;
+    dtype = storage_of(n_paths, dtype);
     Layout L = make_layout(n_paths, n_dates, dtype);
     if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
         return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", L.total);
@@ -489,6 +534,7 @@ int am_price_american(const am_params *params, int64_t n_paths, int32_t n_dates,
     if (!price || !std_err) return fail(AM_EINVAL, "price and std_err must be non-NULL");
     int rc = validate(params, n_paths, n_dates, basis, dtype);
     if (rc) return rc;
+    dtype = storage_of(n_paths, dtype);
     DevState *st = nullptr;
     rc = get_state(&st);
     if (rc) return rc;
@@ -519,6 +565,7 @@ int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_d
     if (rc) return rc;
     if (n_rep < 1 || n_rep > amq::kMaxReps || !h_shifts)
         return fail(AM_EINVAL, "n_rep must be in [1, %d] and shifts non-NULL", amq::kMaxReps);
+    dtype = storage_of(n_paths, dtype);
     Layout L = make_layout(n_paths, n_dates, dtype);
     if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
         return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", L.total);
@@ -618,12 +665,58 @@ long long tune_key(const am_option *opts, int32_t n, am_basis basis, int32_t dty
     return ((long long)dtype << 40) | ((long long)basis.degree << 32) | ((long long)ln << 16) | lw;
 }
 
-int tuned_ppt(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
+bool valid_batch_ppt(int32_t storage, int ppt)
 {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(tune_key(opts, n, basis, dtype));
-    if (it != g_tuned.end()) return it->second;
-    return dtype == AM_FP64 ? 8 : 16;
+    return storage == AM_FP64 ? (ppt == 2 || ppt == 8) : (ppt == 4 || ppt == 16);
+}
+
+int default_batch_ppt(int32_t storage) { return storage == AM_FP64 ? 8 : 16; }
+
+// Paths per thread of the sub-batch stored as `storage` in a batch the caller
+// priced as `dtype`: the tuning hook if it names a tile of this storage
+// type, else the tile am_batch_autotune found for the batch's shape class
+// (it tunes the caller's storage type), else the default.
+int batch_ppt(const am_option *opts, int32_t n, am_basis basis, int32_t dtype, int32_t storage)
+{
+    if (g_batch_ppt && valid_batch_ppt(storage, g_batch_ppt)) return g_batch_ppt;
+    if (storage == dtype) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(tune_key(opts, n, basis, dtype));
+        if (it != g_tuned.end() && valid_batch_ppt(storage, it->second)) return it->second;
+    }
+    return default_batch_ppt(storage);
+}
+
+// A batch as priced: under AM_FP32_BULK the options below AM_FP32_MIN_PATHS
+// paths form a second sub-batch stored in binary64 (part 1); part 0 holds
+// the rest in the caller's storage type.  Each part has its own plan and
+// workspace region.
+struct SplitBatch {
+    int32_t storage[2] = {AM_FP32_BULK, AM_FP64};
+    std::vector<am_option> opts[2];
+    std::vector<int> idx[2];   // caller's index of each option of the part
+    BatchPlan P[2];
+    size_t off[2] = {0, 0};
+    size_t total = 0;
+    int n(int h) const { return (int)opts[h].size(); }
+};
+
+void split_batch(const am_option *opts, int32_t n, int32_t dtype, SplitBatch &B)
+{
+    B.storage[0] = dtype;
+    for (int i = 0; i < n; ++i) {
+        const int h = (dtype == AM_FP32_BULK && storage_of(opts[i].n_paths, dtype) == AM_FP64) ? 1 : 0;
+        B.opts[h].push_back(opts[i]);
+        B.idx[h].push_back(i);
+    }
+    size_t o = 0;
+    for (int h = 0; h < 2; ++h) {
+        if (B.opts[h].empty()) continue;
+        batch_plan(B.opts[h].data(), B.n(h), B.storage[h], B.P[h]);
+        B.off[h] = o;
+        o = align256(o + B.P[h].total);
+    }
+    B.total = o;
 }
 
 int validate_batch(const am_option *opts, int32_t n, am_basis basis, int32_t dtype)
@@ -690,9 +783,9 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
 size_t am_batch_workspace_bytes(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype)
 {
     if (validate_batch(opts, n_opts, basis, dtype)) return 0;
-    BatchPlan P;
-    batch_plan(opts, n_opts, dtype, P);
-    return P.total;
+    SplitBatch B;
+    split_batch(opts, n_opts, dtype, B);
+    return B.total;
 }
 
 }  // extern "C"
@@ -705,11 +798,10 @@ namespace {
 // staging (optional, pinned, staging_bytes) holds the uploaded tables.
 int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
                   char *ws, const BatchPlan &P, hipStream_t stream, int grid_cap, bool cooperative,
-                  char *staging, size_t staging_bytes)
+                  char *staging, size_t staging_bytes, int ppt)
 {
     int rc = AM_OK;
     const int fp64 = dtype == AM_FP64;
-    const int ppt = g_batch_ppt ? g_batch_ppt : tuned_ppt(opts, n_opts, basis, dtype);
     const int64_t tile = (int64_t)amq::kWG * ppt;
     if (kBatchTileAlign % tile != 0) return fail(AM_EINVAL, "batch tile %lld does not divide the row padding", (long long)tile);
     const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, basis.kind == AM_BASIS_LAGUERRE, ppt, basis.degree);
@@ -820,6 +912,86 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     return AM_OK;
 }
 
+// Bytes of pinned staging one part's tables need (descriptors, tile table,
+// generation units).
+size_t staging_bytes_for(const BatchPlan &P, int n)
+{
+    return align256((size_t)n * sizeof(amq::BatchOpt)) + align256((size_t)P.total_blocks * 4) +
+           (size_t)P.max_units * sizeof(amq::GenUnit) + 256;
+}
+
+// Enqueue both parts of a split batch on `stream` (part 0 first).  ppt[h]:
+// tile of part h (0: batch_ppt's choice); grid_cap[h]: cap on part h's
+// persistent grid (0: the device's resident capacity); staging (optional,
+// pinned) holds both parts' tables, part 1's after part 0's.
+int enqueue_split(DevState *st, const SplitBatch &B, am_basis basis, int32_t dtype, char *ws,
+                  hipStream_t stream, const int *grid_cap, bool cooperative, char *staging,
+                  size_t staging_bytes, const int *ppt_in)
+{
+    size_t so = 0;
+    for (int h = 0; h < 2; ++h) {
+        if (!B.n(h)) continue;
+        const int ppt = ppt_in && ppt_in[h] ? ppt_in[h]
+                                            : batch_ppt(B.opts[h].data(), B.n(h), basis, dtype, B.storage[h]);
+        const size_t need = staging_bytes_for(B.P[h], B.n(h));
+        char *stg = staging && so + need <= staging_bytes ? staging + so : nullptr;
+        int rc = enqueue_batch(st, B.opts[h].data(), B.n(h), basis, B.storage[h], ws + B.off[h], B.P[h], stream,
+                               grid_cap ? grid_cap[h] : 0, cooperative, stg, stg ? need : 0, ppt);
+        if (rc) return rc;
+        so += align256(need);
+    }
+    return AM_OK;
+}
+
+// Enqueue the device-to-host copies of both parts' results into h_res:
+// part 0's [n0][8] doubles and its 8-double sync block, then part 1's.
+int enqueue_split_results(const SplitBatch &B, char *ws, double *h_res, hipStream_t stream)
+{
+    size_t o = 0;
+    for (int h = 0; h < 2; ++h) {
+        if (!B.n(h)) continue;
+        char *w = ws + B.off[h];
+        HIP_TRY(hipMemcpyAsync(h_res + o, w + B.P[h].off_res, (size_t)B.n(h) * 64, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(h_res + o + (size_t)B.n(h) * 8, w + B.P[h].off_gsync, 64, hipMemcpyDeviceToHost,
+                               stream));
+        o += (size_t)B.n(h) * 8 + 8;
+    }
+    return AM_OK;
+}
+
+// Doubles enqueue_split_results writes.
+size_t split_results_doubles(const SplitBatch &B)
+{
+    size_t o = 0;
+    for (int h = 0; h < 2; ++h)
+        if (B.n(h)) o += (size_t)B.n(h) * 8 + 8;
+    return o;
+}
+
+// Read results written by enqueue_split_results back into the caller's order
+// (price, std_err per option).  Returns AM_ETIMEOUT if a part's bounded
+// wait ran out.
+int scatter_split_results(const SplitBatch &B, const double *h_res, double *h_out, int32_t *status)
+{
+    size_t o = 0;
+    int rc = AM_OK;
+    for (int h = 0; h < 2; ++h) {
+        if (!B.n(h)) continue;
+        const uint32_t *gs = (const uint32_t *)(h_res + o + (size_t)B.n(h) * 8);
+        const bool timed_out = gs[1] != 0u;
+        if (timed_out) rc = fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
+        for (int j = 0; j < B.n(h); ++j) {
+            const int i = B.idx[h][j];
+            const double pr = h_res[o + (size_t)j * 8], se = h_res[o + (size_t)j * 8 + 1];
+            if (h_out) { h_out[2 * i] = pr; h_out[2 * i + 1] = se; }
+            if (status) status[i] = timed_out ? AM_ETIMEOUT : (isfinite(pr) ? AM_OK : AM_EDEVICE);
+            if (!timed_out && !isfinite(pr) && rc == AM_OK) rc = fail(AM_EDEVICE, "option %d: non-finite result", i);
+        }
+        o += (size_t)B.n(h) * 8 + 8;
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -829,30 +1001,23 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
 {
     int rc = validate_batch(opts, n_opts, basis, dtype);
     if (rc) return rc;
-    BatchPlan P;
-    batch_plan(opts, n_opts, dtype, P);
-    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
-        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    SplitBatch B;
+    split_batch(opts, n_opts, dtype, B);
+    if (!d_workspace || ws_bytes < B.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", B.total);
     DevState *st = nullptr;
     rc = get_state(&st);
     if (rc) return rc;
     char *ws = (char *)d_workspace;
     hipStream_t stream = (hipStream_t)hip_stream;
-    rc = enqueue_batch(st, opts, n_opts, basis, dtype, ws, P, stream, 0, true, nullptr, 0);
+    rc = enqueue_split(st, B, basis, dtype, ws, stream, nullptr, true, nullptr, 0, nullptr);
     if (rc) return rc;
     if (!h_out) return AM_OK;
-    std::vector<double> res((size_t)n_opts * 8);
-    uint32_t gs[16];
-    HIP_TRY(hipMemcpyAsync(res.data(), ws + P.off_res, res.size() * 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(gs, ws + P.off_gsync, sizeof gs, hipMemcpyDeviceToHost, stream));
+    std::vector<double> res(split_results_doubles(B));
+    rc = enqueue_split_results(B, ws, res.data(), stream);
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(stream));
-    if (gs[1] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
-    for (int i = 0; i < n_opts; ++i) {
-        h_out[2 * i] = res[(size_t)i * 8];
-        h_out[2 * i + 1] = res[(size_t)i * 8 + 1];
-        if (!isfinite(h_out[2 * i])) return fail(AM_EDEVICE, "option %d: non-finite result", i);
-    }
-    return AM_OK;
+    return scatter_split_results(B, res.data(), h_out, nullptr);
 }
 
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
@@ -865,10 +1030,10 @@ int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int
 {
     int rc = validate_batch(opts, n_opts, basis, dtype);
     if (rc) return rc;
-    BatchPlan P;
-    batch_plan(opts, n_opts, dtype, P);
-    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
-        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    SplitBatch B;
+    split_batch(opts, n_opts, dtype, B);
+    if (!d_workspace || ws_bytes < B.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", B.total);
     DevState *st = nullptr;
     rc = get_state(&st);
     if (rc) return rc;
@@ -885,8 +1050,8 @@ int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int
         double ms = 0.0;
         for (int rep = 0; rep < 3 && rc == AM_OK; ++rep) {    // first run warms up
             if (hipEventRecord(e0, stream) != hipSuccess) rc = AM_EDEVICE;
-            if (!rc) rc = enqueue_batch(st, opts, n_opts, basis, dtype, (char *)d_workspace, P, stream, 0,
-                                        true, nullptr, 0);
+            if (!rc) rc = enqueue_split(st, B, basis, dtype, (char *)d_workspace, stream, nullptr, true, nullptr,
+                                        0, nullptr);
             if (!rc && hipEventRecord(e1, stream) != hipSuccess) rc = AM_EDEVICE;
             if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = AM_EDEVICE;
             float t = 0.f;
@@ -916,6 +1081,7 @@ int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int
 // pinned staging, generation, the persistent sweep (normal launch, grid
 // within the resident capacity) and the result download.
 struct am_batch_graph {
+    std::unique_ptr<SplitBatch> split;   // the parts captured and their result layout
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -932,10 +1098,10 @@ int am_batch_graph_create(const am_option *opts, int32_t n_opts, am_basis basis,
     if (!out) return fail(AM_EINVAL, "out is NULL");
     int rc = validate_batch(opts, n_opts, basis, dtype);
     if (rc) return rc;
-    BatchPlan P;
-    batch_plan(opts, n_opts, dtype, P);
-    if (!d_workspace || ws_bytes < P.total || ((uintptr_t)d_workspace & 255u))
-        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", P.total);
+    SplitBatch B;
+    split_batch(opts, n_opts, dtype, B);
+    if (!d_workspace || ws_bytes < B.total || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "batch workspace must be >= %zu bytes and 256-byte aligned", B.total);
     DevState *st = nullptr;
     rc = get_state(&st);
     if (rc) return rc;
@@ -946,22 +1112,21 @@ int am_batch_graph_create(const am_option *opts, int32_t n_opts, am_basis basis,
     }
     std::unique_ptr<am_batch_graph> g(new am_batch_graph);
     g->n = n_opts;
-    const size_t stage = align256((size_t)n_opts * sizeof(amq::BatchOpt)) + align256((size_t)P.total_blocks * 4) +
-                         (size_t)P.max_units * sizeof(amq::GenUnit) + 4096;
+    g->split.reset(new SplitBatch(B));
+    size_t stage = 0;
+    for (int h = 0; h < 2; ++h)
+        if (B.n(h)) stage += align256(staging_bytes_for(B.P[h], B.n(h)));
     if (hipHostMalloc((void **)&g->staging, stage, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_res, (size_t)n_opts * 64 + 64, hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void **)&g->h_res, split_results_doubles(B) * 8, hipHostMallocDefault) != hipSuccess)
         return fail(AM_ENOMEM, "pinned buffers for the batch graph failed");
     HIP_TRY(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     char *ws = (char *)d_workspace;
-    rc = enqueue_batch(st, opts, n_opts, basis, dtype, ws, P, cs, 0, false, g->staging, stage);
-    if (rc == AM_OK) {
-        if (hipMemcpyAsync(g->h_res, ws + P.off_res, (size_t)n_opts * 64, hipMemcpyDeviceToHost, cs) != hipSuccess ||
-            hipMemcpyAsync(g->h_res + (size_t)n_opts * 8, ws + P.off_gsync, 64, hipMemcpyDeviceToHost, cs) != hipSuccess)
-            rc = fail(AM_EDEVICE, "result download could not be captured");
-    }
+    rc = enqueue_split(st, B, basis, dtype, ws, cs, nullptr, false, g->staging, stage, nullptr);
+    if (rc == AM_OK && enqueue_split_results(B, ws, g->h_res, cs) != AM_OK)
+        rc = fail(AM_EDEVICE, "result download could not be captured");
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
@@ -986,13 +1151,7 @@ int am_batch_graph_results(am_batch_graph *g, double *h_out)
 {
     if (!g || !h_out) return fail(AM_EINVAL, "graph and h_out must be non-NULL");
     HIP_TRY(hipEventSynchronize(g->done));
-    const uint32_t *gs = (const uint32_t *)(g->h_res + (size_t)g->n * 8);
-    if (gs[1] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
-    for (int i = 0; i < g->n; ++i) {
-        h_out[2 * i] = g->h_res[(size_t)i * 8];
-        h_out[2 * i + 1] = g->h_res[(size_t)i * 8 + 1];
-    }
-    return AM_OK;
+    return scatter_split_results(*g->split, g->h_res, h_out, nullptr);
 }
 
 int am_batch_graph_destroy(am_batch_graph *g)
@@ -1071,10 +1230,12 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     char *staging = nullptr;          // pinned: uploaded tables
-    double *h_res = nullptr;          // pinned: [max][8] results + sync words
+    double *h_res = nullptr;          // pinned: per part [n][8] results + 8 sync doubles
     size_t staging_bytes = 0;
     bool busy = false;
+    bool exclusive = false;           // runs alone on the whole device
     std::vector<Request> reqs;
+    SplitBatch split;                 // the launched parts (result layout)
     size_t off = 0, bytes = 0;
     double t_launch = 0.0;
 };
@@ -1087,7 +1248,9 @@ struct am_server {
     char *pool = nullptr;
     PoolAlloc alloc;
     std::vector<Slot> slots;
-    int grid_cap = 0;
+    int grid_cap[2] = {0, 0};         // per part: 1/n_streams of the resident capacity
+    int full_cap[2] = {0, 0};         // per part: the whole device's resident capacity
+    int ppt[2] = {0, 0};              // per part: batch tile (paths per thread)
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request> pending;
@@ -1104,15 +1267,17 @@ namespace {
 
 void finish_slot(am_server *sv, Slot &sl, std::vector<am_result> &out)
 {
-    const uint32_t *gs = (const uint32_t *)(sl.h_res + (size_t)sl.reqs.size() * 8);
     const double t = now_s();
+    std::vector<double> price(sl.reqs.size() * 2, 0.0);
+    std::vector<int32_t> status(sl.reqs.size(), AM_OK);
+    (void)scatter_split_results(sl.split, sl.h_res, price.data(), status.data());
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
         am_result r;
         memset(&r, 0, sizeof r);
         r.request_id = sl.reqs[i].id;
-        r.price = sl.h_res[i * 8];
-        r.std_err = sl.h_res[i * 8 + 1];
-        r.status = gs[1] != 0u ? AM_ETIMEOUT : (isfinite(r.price) ? AM_OK : AM_EDEVICE);
+        r.price = price[2 * i];
+        r.std_err = price[2 * i + 1];
+        r.status = status[i];
         r.t_arrival = sl.reqs[i].t_arrival;
         r.t_launch = sl.t_launch;
         r.t_done = t;
@@ -1120,51 +1285,96 @@ void finish_slot(am_server *sv, Slot &sl, std::vector<am_result> &out)
     }
     sv->alloc.release(sl.off, sl.bytes);
     sl.reqs.clear();
+    sl.split = SplitBatch();
     sl.busy = false;
+    sl.exclusive = false;
+}
+
+void refuse(const Request &q, int32_t status, std::vector<am_result> &out)
+{
+    am_result r;
+    memset(&r, 0, sizeof r);
+    r.request_id = q.id;
+    r.status = status;
+    r.t_arrival = q.t_arrival;
+    r.t_done = now_s();
+    out.push_back(r);
+}
+
+// Sweep tiles one served request needs (the server's fixed tile per part).
+int64_t request_tiles(const am_server *sv, const am_option &o, int *part)
+{
+    const int h = (sv->cfg.dtype == AM_FP32_BULK && storage_of(o.n_paths, sv->cfg.dtype) == AM_FP64) ? 1 : 0;
+    if (part) *part = h;
+    const int64_t tile = (int64_t)amq::kWG * sv->ppt[h];
+    return (o.n_paths + tile - 1) / tile;
 }
 
 // Launch the longest admissible prefix of the pending queue on slot `sl`.
-// Returns true if something was launched.
+// A request whose sweep needs more groups than a stream's share of the
+// device goes alone, on the whole device, once every slot is idle; nothing
+// launches while it runs.  Returns true if something was launched.
 bool launch_some(am_server *sv, Slot &sl, std::deque<Request> &pend, std::vector<am_result> &out)
 {
     const am_server_config &c = sv->cfg;
+    bool any_busy = false;
+    for (auto &o : sv->slots) {
+        if (o.busy && o.exclusive) return false;
+        any_busy = any_busy || o.busy;
+    }
     std::vector<am_option> opts;
     std::vector<Request> take;
     double work = 0.0;
+    bool exclusive = false;
     for (size_t i = 0; i < pend.size() && (int)take.size() < c.max_batch_requests; ++i) {
+        int h = 0;
+        const bool big = request_tiles(sv, pend[i].opt, &h) > sv->grid_cap[h];
+        if (big) {
+            if (!take.empty()) break;          // the prefix stops before it
+            if (any_busy) return false;        // waits for the device to drain
+            exclusive = true;
+        }
         const double w = (double)pend[i].opt.n_paths * pend[i].opt.n_dates;
         if (!take.empty() && work + w > c.max_batch_path_steps) break;
         take.push_back(pend[i]);
         opts.push_back(pend[i].opt);
         work += w;
+        if (exclusive) break;
     }
     while (!take.empty()) {
-        BatchPlan P;
-        batch_plan(opts.data(), (int32_t)opts.size(), c.dtype, P);
+        SplitBatch B;
+        split_batch(opts.data(), (int32_t)opts.size(), c.dtype, B);
         size_t off = 0;
-        if (sv->alloc.alloc(P.total, &off)) {
+        if (sv->alloc.alloc(B.total, &off)) {
             sl.off = off;
-            sl.bytes = P.total;
+            sl.bytes = B.total;
             sl.reqs = take;
+            sl.split = B;
+            sl.exclusive = exclusive;
             sl.t_launch = now_s();
-            int rc = enqueue_batch(sv->st, opts.data(), (int32_t)opts.size(), c.basis, c.dtype,
-                                   sv->pool + off, P, sl.stream, sv->grid_cap, false, sl.staging,
-                                   sl.staging_bytes);
-            if (rc == AM_OK) {
-                char *ws = sv->pool + off;
-                rc = hipMemcpyAsync(sl.h_res, ws + P.off_res, opts.size() * 8 * 8, hipMemcpyDeviceToHost,
-                                    sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
-                if (rc == AM_OK)
-                    rc = hipMemcpyAsync(sl.h_res + opts.size() * 8, ws + P.off_gsync, 64,
-                                        hipMemcpyDeviceToHost, sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
-                if (rc == AM_OK)
-                    rc = hipEventRecord(sl.done, sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
-            }
+            char *ws = sv->pool + off;
+            int rc = enqueue_split(sv->st, sl.split, c.basis, c.dtype, ws, sl.stream,
+                                   exclusive ? sv->full_cap : sv->grid_cap, false, sl.staging, sl.staging_bytes,
+                                   sv->ppt);
+            if (rc == AM_OK) rc = enqueue_split_results(sl.split, ws, sl.h_res, sl.stream);
+            if (rc == AM_OK) rc = hipEventRecord(sl.done, sl.stream) == hipSuccess ? AM_OK : AM_EDEVICE;
             if (rc != AM_OK) {
-                sv->alloc.release(off, P.total);
-                sv->fatal = rc;
-                sv->fatal_msg = g_err;
-                return false;
+                // nothing of this batch may still run when its memory is reused
+                (void)hipStreamSynchronize(sl.stream);
+                sv->alloc.release(off, B.total);
+                sl.reqs.clear();
+                sl.split = SplitBatch();
+                sl.exclusive = false;
+                if (rc == AM_EDEVICE) {        // the device itself failed: stop serving
+                    sv->fatal = rc;
+                    sv->fatal_msg = g_err;
+                    return false;
+                }
+                for (size_t i = 0; i < take.size(); ++i) {   // only these requests fail
+                    refuse(take[i], rc, out);
+                    pend.pop_front();
+                }
+                return true;
             }
             sl.busy = true;
             for (size_t i = 0; i < take.size(); ++i) pend.pop_front();
@@ -1175,15 +1385,8 @@ bool launch_some(am_server *sv, Slot &sl, std::deque<Request> &pend, std::vector
         }
         if (take.size() == 1) {
             // a lone request that does not fit even an empty pool is refused
-            bool idle = sv->alloc.used == 0;
-            if (idle) {
-                am_result r;
-                memset(&r, 0, sizeof r);
-                r.request_id = take[0].id;
-                r.status = AM_ENOMEM;
-                r.t_arrival = take[0].t_arrival;
-                r.t_done = now_s();
-                out.push_back(r);
+            if (sv->alloc.used == 0) {
+                refuse(take[0], AM_ENOMEM, out);
                 pend.pop_front();
             }
             return false;
@@ -1252,11 +1455,19 @@ int am_server_create(const am_server_config *cfg, am_server **out)
     if (hipMalloc((void **)&sv->pool, cfg->hbm_budget_bytes) != hipSuccess)
         return fail(AM_ENOMEM, "hipMalloc of the %zu-byte serving pool failed", cfg->hbm_budget_bytes);
     sv->alloc.init(cfg->hbm_budget_bytes);
-    const int fp64 = cfg->dtype == AM_FP64;
-    const int ppt = fp64 ? 8 : 16;
-    const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, cfg->basis.kind == AM_BASIS_LAGUERRE, ppt, cfg->basis.degree);
-    if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel");
-    sv->grid_cap = per_cu * st->num_cu / cfg->n_streams;   // in-flight grids fit together
+    // part 0 in the configured storage, part 1 (FP32 bulk only) the small
+    // requests stored in binary64; each with the default tile, and grids
+    // capped so that the in-flight ones fit on the device together
+    for (int h = 0; h < 2; ++h) {
+        const int32_t storage = h == 0 ? cfg->dtype : AM_FP64;
+        const int fp64 = storage == AM_FP64;
+        sv->ppt[h] = default_batch_ppt(storage);
+        const int per_cu = amq::sweep_batch_blocks_per_cu(fp64, cfg->basis.kind == AM_BASIS_LAGUERRE, sv->ppt[h],
+                                                          cfg->basis.degree);
+        if (per_cu <= 0) return fail(AM_EDEVICE, "no batch sweep kernel");
+        sv->full_cap[h] = per_cu * st->num_cu;
+        sv->grid_cap[h] = sv->full_cap[h] / cfg->n_streams;
+    }
     sv->slots.resize(cfg->n_streams);
     for (auto &sl : sv->slots) {
         HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
@@ -1264,8 +1475,12 @@ int am_server_create(const am_server_config *cfg, am_server **out)
         sl.staging_bytes = 8u << 20;
         if (hipHostMalloc((void **)&sl.staging, sl.staging_bytes, hipHostMallocDefault) != hipSuccess)
             return fail(AM_ENOMEM, "pinned staging allocation failed");
-        if (hipHostMalloc((void **)&sl.h_res, (size_t)cfg->max_batch_requests * 64 + 64, hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void **)&sl.h_res, (size_t)cfg->max_batch_requests * 64 + 128, hipHostMallocDefault) != hipSuccess)
             return fail(AM_ENOMEM, "pinned result allocation failed");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        ++g_live_servers;
     }
     am_server *p = sv.release();
     p->th = std::thread(server_loop, p);
@@ -1278,6 +1493,11 @@ int am_server_submit(am_server *sv, const am_option *opt, uint64_t request_id, d
     if (!sv || !opt) return fail(AM_EINVAL, "server and option must be non-NULL");
     int rc = validate(&opt->params, opt->n_paths, opt->n_dates, sv->cfg.basis, sv->cfg.dtype);
     if (rc) return rc;
+    int h = 0;
+    const int64_t tiles = request_tiles(sv, *opt, &h);
+    if (tiles > sv->full_cap[h])
+        return fail(AM_EDIM, "request needs %lld sweep workgroups; the device holds %d resident", (long long)tiles,
+                    sv->full_cap[h]);
     Request r;
     r.opt = *opt;
     r.id = request_id;
@@ -1336,6 +1556,10 @@ int am_server_destroy(am_server *sv)
     }
     if (sv->pool) (void)hipFree(sv->pool);
     delete sv;
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        --g_live_servers;
+    }
     return rc;
 }
 
@@ -1364,6 +1588,50 @@ int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left, 
 
 void am_debug_set_spin_limit(uint32_t spins) { g_spin_limit = spins; }
 
+int am_shutdown(void)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        if (g_live_servers > 0) return fail(AM_EINVAL, "%d server(s) still running", g_live_servers);
+    }
+    int rc = AM_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        int cur = -1;
+        const bool restore = !g_devs.empty() && hipGetDevice(&cur) == hipSuccess;
+        for (auto &kv : g_devs) {
+            DevState *st = kv.second.get();
+            if (hipSetDevice(st->dev) != hipSuccess) {
+                rc = fail(AM_EDEVICE, "hipSetDevice(%d) failed during shutdown", st->dev);
+                continue;
+            }
+            // the library's own work first: the synchronous stream and the
+            // last single-option sweep on any stream
+            if (st->stream) (void)hipStreamSynchronize(st->stream);
+            if (st->persist_done) (void)hipEventSynchronize(st->persist_done);
+            for (auto &sc : st->sched) (void)hipFree(sc.second);
+            st->sched.clear();
+            if (st->d_V) (void)hipFree(st->d_V);
+            if (st->ws) (void)hipFree(st->ws);
+            if (st->persist_done) (void)hipEventDestroy(st->persist_done);
+            if (st->stream) (void)hipStreamDestroy(st->stream);
+            st->d_V = nullptr;
+            st->ws = nullptr;
+            st->persist_done = nullptr;
+            st->stream = nullptr;
+        }
+        g_devs.clear();
+        if (restore) (void)hipSetDevice(cur);
+    }
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    for (void *ptr : g_pinned_all) (void)hipHostFree(ptr);
+    for (hipEvent_t e : g_events_all) (void)hipEventDestroy(e);
+    g_pinned_all.clear();
+    g_events_all.clear();
+    ++g_generation;   // threads drop their cached pointers on next use
+    return rc;
+}
+
 int am_profile_enable(int32_t on)
 {
     g_prof.on = on != 0;
@@ -1374,6 +1642,14 @@ int am_profile_enable(int32_t on)
 int am_profile_read(double ms[2], int64_t *calls)
 {
     if (!ms || !calls) return fail(AM_EINVAL, "ms and calls must be non-NULL");
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        if (g_prof.gen != g_generation) {   // events released by am_shutdown
+            g_prof.pool.clear();
+            g_prof.used = 0;
+            g_prof.gen = g_generation;
+        }
+    }
     double g = 0.0, w = 0.0;
     for (size_t i = 0; i < g_prof.used; ++i) {
         ProfRec &r = g_prof.pool[i];

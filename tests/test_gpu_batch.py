@@ -134,3 +134,27 @@ def test_batch_autotune_and_graph_replay(amq, orc, pricer):
         g.close()
     finally:
         amq.am_debug_set_batch_ppt(0)
+
+
+def test_batch_fp32_small_paths(amq, orc, pricer):
+    # the served workload's lower path range (2^12 and up): options below
+    # AM_FP32_MIN_PATHS paths form a sub-batch stored in binary64.  Every
+    # option meets the FP32-bulk tolerance, and each small option is bitwise
+    # its result in an FP64 batch
+    specs = batch_options(24, seed=29, log2_paths=(12.0, 14.6), dates=(3, 40))
+    small = [i for i, d in enumerate(specs) if d["n_paths"] < amq.AM_FP32_MIN_PATHS]
+    log(f"  {len(small)} of {len(specs)} options below {amq.AM_FP32_MIN_PATHS} paths")
+    assert 0 < len(small) < len(specs)
+    b = amq.make_basis("monomial", 2)
+    got = pricer.price_batch(amq.make_options(specs), b, "fp32")
+    worst = 0.0
+    for i, d in enumerate(specs):
+        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        err = abs(got[i, 0] - want.price)
+        worst = max(worst, err)
+        assert err <= TOL["fp32"], (i, d, got[i], want.price)
+    log(f"    worst |gpu - oracle| = {worst:.3e}")
+    g64 = pricer.price_batch(amq.make_options([specs[i] for i in small]), b, "fp64")
+    for j, i in enumerate(small):
+        assert got[i, 0] == g64[j, 0] and got[i, 1] == g64[j, 1], i

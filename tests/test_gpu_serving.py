@@ -81,3 +81,53 @@ def test_serving_refuses_request_larger_than_budget(amq):
         srv.submit(big[0], 7)
         r = _collect(srv, 1)[7]
     assert r["status"] == amq.AM_ENOMEM
+
+
+def test_serving_fp32_small_paths(amq, orc):
+    # the served workload's lower path range, FP32 bulk: requests below
+    # AM_FP32_MIN_PATHS paths run in a binary64 part of their batch; every
+    # result within the FP32-bulk tolerance of the oracle
+    specs = batch_options(24, seed=31, log2_paths=(12.0, 14.6), dates=(12, 40))
+    assert any(d["n_paths"] < amq.AM_FP32_MIN_PATHS for d in specs)
+    b = amq.make_basis("monomial", 2)
+    opts = amq.make_options(specs)
+    with amq.Server(256 << 20, b, "fp32", n_streams=2, max_batch_requests=6) as srv:
+        for i in range(len(specs)):
+            srv.submit(opts[i], i)
+        got = _collect(srv, len(specs))
+    worst = 0.0
+    for i, d in enumerate(specs):
+        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        assert got[i]["status"] == 0
+        err = abs(got[i]["price"] - want.price)
+        worst = max(worst, err)
+        assert err <= 2e-3, (i, d, got[i]["price"], want.price)
+    log(f"  worst |served - oracle| = {worst:.3e}")
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_serving_request_larger_than_a_stream_share(amq, dtype):
+    # eight streams: a 2^20-path request needs more sweep groups than one
+    # stream's share of the device, so it runs alone on the whole device;
+    # the smaller requests around it are served as usual, and every result is
+    # the batch result of the request alone (same tile)
+    b = amq.make_basis("monomial", 2)
+    specs = batch_options(6, seed=37, log2_paths=(14.0, 15.0), dates=(12, 30))
+    big = dict(S0=100.0, K=105.0, r=0.03, sigma=0.25, T=1.0, is_call=False, n_paths=1 << 20, n_dates=24)
+    specs = specs[:2] + [big] + specs[2:4] + [dict(big, K=95.0, is_call=True)] + specs[4:]
+    opts = amq.make_options(specs)
+    with amq.Server(8 << 30, b, dtype, n_streams=8, max_batch_requests=4) as srv:
+        for i in range(len(specs)):
+            srv.submit(opts[i], i)
+        got = _collect(srv, len(specs))
+    pr = amq.Pricer(0)
+    amq.am_debug_set_batch_ppt(16 if dtype == "fp32" else 8)
+    try:
+        for i, d in enumerate(specs):
+            assert got[i]["status"] == 0, (i, got[i])
+            alone = pr.price_batch(amq.make_options([d]), b, dtype)
+            assert got[i]["price"] == alone[0, 0], (i, got[i]["price"], alone[0, 0])
+    finally:
+        amq.am_debug_set_batch_ppt(0)
+

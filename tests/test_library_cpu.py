@@ -40,6 +40,25 @@ def test_max_dates(amq):
     assert amq.am_max_dates() >= 365
 
 
+def test_storage_rule(amq):
+    # FP32-bulk requests below AM_FP32_MIN_PATHS paths are stored in binary64,
+    # and their workspace is the binary64 one
+    lo = amq.AM_FP32_MIN_PATHS
+    assert lo == 1 << 14
+    assert amq.am_storage_dtype(lo - 1, "fp32") == amq.AM_FP64
+    assert amq.am_storage_dtype(lo, "fp32") == amq.AM_FP32_BULK
+    assert amq.am_storage_dtype(10, "fp64") == amq.AM_FP64
+    assert amq.lib().am_storage_dtype(1000, 7) == -1
+    b = amq.make_basis("monomial", 2)
+    assert amq.am_workspace_bytes(lo - 1, 20, b, "fp32") == amq.am_workspace_bytes(lo - 1, 20, b, "fp64")
+    assert amq.am_workspace_bytes(lo, 20, b, "fp32") < amq.am_workspace_bytes(lo, 20, b, "fp64")
+
+
+def test_shutdown_without_device_work(amq):
+    # nothing set up yet on this host: releases nothing, touches no device
+    assert amq.lib().am_shutdown() == amq.AM_OK
+
+
 @pytest.mark.parametrize("N,M,dt", [(16384, 50, "fp64"), (1 << 20, 100, "fp32"), (1000, 3, "fp64")])
 def test_workspace_layout(amq, N, M, dt):
     b = amq.make_basis("monomial", 2)
