@@ -137,6 +137,39 @@ int am_price_american_ex(const am_params *params, int64_t n_paths, int32_t n_dat
                          am_basis basis, int32_t dtype, void *d_workspace, size_t ws_bytes,
                          void *hip_stream, double *h_out);
 
+/* Size of the fixed device workspace of am_price_american_noalloc: 128 MiB
+ * on each device the library runs on, held until the process ends. */
+enum { AM_SCRATCH_BYTES = 134217728 };
+
+/* Set up the current device for the library: direction-number table,
+ * stream, the event that orders single-option sweeps, the device address of
+ * the allocation-free entry point's workspace, and every single-option
+ * kernel's code loaded on the device.  Allocates; idempotent; any thread.
+ * Needed once per device (and again after am_shutdown) before
+ * am_price_american_noalloc; the other entry points set up lazily. */
+int am_init(void);
+
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): prices
+ * exactly as am_price_american_ex (same kernels, same tiles: bitwise the
+ * same price and std_err) but its workspace is a fixed array of
+ * AM_SCRATCH_BYTES that the library holds on the device, and the call
+ * allocates nothing: no hipMalloc, hipFree, hipHostMalloc, event or stream
+ * creation.  am_init must have run on the current device (AM_EINVAL
+ * otherwise).  The bridge schedule for n_dates is copied into the array
+ * from host memory on hip_stream (a hipStream_t; NULL is the null stream);
+ * the call waits for hip_stream and writes h_out[0] = price, h_out[1] =
+ * std_err (h_out must be non-NULL).  A shape whose am_workspace_bytes plus
+ * 64 * n_dates exceeds AM_SCRATCH_BYTES fails with AM_EWORKSPACE (for
+ * binary64 storage about 2^17 paths x 125 dates, binary32 2^18 x 125).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the kernels clear what has to start at zero); calls that
+ * overlap on one device, from two threads or on two streams, race on it and
+ * must be serialised by the caller.  am_profile_* does not time this entry
+ * point. */
+int am_price_american_noalloc(const am_params *params, int64_t n_paths, int32_t n_dates,
+                              am_basis basis, int32_t dtype, void *hip_stream, double *h_out);
+
 /* Randomised quasi-Monte Carlo (reading of Section III.D, where the
  * quasi-random arrays are permuted by a linear congruential generator to make
  * the per-path samples statistically independent): n_rep independent

@@ -25,6 +25,7 @@ AM_BASIS_MONOMIAL, AM_BASIS_LAGUERRE = 0, 1
 AM_FP64, AM_FP32_BULK = 0, 1
 AM_MAX_DEGREE = 6
 AM_FP32_MIN_PATHS = 16384   # FP32-bulk requests below this path count are stored in binary64
+AM_SCRATCH_BYTES = 134217728   # fixed device workspace of am_price_american_noalloc
 REC = 40            # doubles per per-date record in the workspace
 
 _BASIS_NAMES = {"monomial": AM_BASIS_MONOMIAL, "laguerre": AM_BASIS_LAGUERRE}
@@ -110,6 +111,11 @@ def lib():
         L.am_price_american_ex.argtypes = [P(am_params), i64, i32, am_basis, i32, ctypes.c_void_p,
                                            sz, ctypes.c_void_p, P(dbl)]
         L.am_price_american_ex.restype = ctypes.c_int
+        L.am_init.argtypes = []
+        L.am_init.restype = ctypes.c_int
+        L.am_price_american_noalloc.argtypes = [P(am_params), i64, i32, am_basis, i32, ctypes.c_void_p,
+                                                P(dbl)]
+        L.am_price_american_noalloc.restype = ctypes.c_int
         L.am_price_american_rqmc.argtypes = [P(am_params), i64, i32, am_basis, i32, i32,
                                              P(ctypes.c_uint32), ctypes.c_void_p, sz,
                                              ctypes.c_void_p, P(dbl)]
@@ -246,6 +252,24 @@ def am_price_american_ex(params: am_params, n_paths: int, n_dates: int, basis: a
     if wait:
         return out[0], out[1]
     return None
+
+
+def am_init() -> None:
+    """Set up the current device (needed before am_price_american_noalloc)."""
+    _check(lib().am_init())
+
+
+def am_price_american_noalloc(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
+                              stream=None) -> Tuple[float, float]:
+    """Allocation-free pricing in the library's fixed device workspace, on a
+    torch stream (None: the current stream); returns (price, std_err)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = (ctypes.c_double * 2)()
+    _check(lib().am_price_american_noalloc(ctypes.byref(params), int(n_paths), int(n_dates), basis,
+                                           _dtype(dtype), ctypes.c_void_p(stream.cuda_stream), out))
+    return out[0], out[1]
 
 
 def am_price_american_rqmc(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,

@@ -26,6 +26,13 @@
 extern "C" const uint32_t amq_sobol_v32[];
 extern "C" const uint32_t amq_sobol_v32_dims;
 
+// Workspace of the allocation-free entry point (am_price_american_noalloc):
+// AM_SCRATCH_BYTES on every device the library runs on, held until the
+// process ends.  In host code this name is only a handle for the runtime:
+// am_init resolves each device's own copy with hipGetSymbolAddress and every
+// host-side use (kernel arguments, copies) goes through DevState::scratch.
+static __device__ __align__(256) unsigned char scratch[AM_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err = "no error";
@@ -177,6 +184,10 @@ struct DevState {
     std::mutex persist_mu;
     hipEvent_t persist_done = nullptr;
     hipStream_t persist_stream = nullptr;
+    // allocation-free entry point: this device's copy of `scratch` (set by
+    // am_init) and host-side bridge schedules for it, built once per date count
+    char *scratch = nullptr;
+    std::map<int, std::vector<amq::BridgeNode>> host_sched;
 };
 
 std::mutex g_dev_mu;
@@ -204,6 +215,16 @@ int get_state(DevState **out)
     *out = st.get();
     g_devs[dev] = std::move(st);
     return AM_OK;
+}
+
+// The current device's state if a call has set it up, else nullptr (creates nothing).
+DevState *find_state()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_devs.find(dev);
+    return it == g_devs.end() ? nullptr : it->second.get();
 }
 
 int get_schedule(DevState *st, int M, const amq::BridgeNode **out)
@@ -340,16 +361,23 @@ int prof_slot(ProfRec **out)
 }
 
 // Enqueue both kernels; result stays in the workspace.
+// noalloc_sched: the allocation-free entry point passes the schedule it
+// placed in its scratch memory; then nothing here allocates or creates a
+// HIP object (no schedule cache entry, no profiling events, the ordering
+// event made by am_init).
 int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, int32_t dtype,
-            char *ws, const Layout &L, hipStream_t stream, int rep = -1, int n_rep = 0)
+            char *ws, const Layout &L, hipStream_t stream, int rep = -1, int n_rep = 0,
+            const amq::BridgeNode *noalloc_sched = nullptr)
 {
     const int fp64 = dtype == AM_FP64;
     Plan plan;
     int rc = choose_plan(st, N, fp64, b.kind == AM_BASIS_LAGUERRE, b.degree, &plan);
     if (rc) return rc;
-    const amq::BridgeNode *sched = nullptr;
-    rc = get_schedule(st, M, &sched);
-    if (rc) return rc;
+    const amq::BridgeNode *sched = noalloc_sched;
+    if (!sched) {
+        rc = get_schedule(st, M, &sched);
+        if (rc) return rc;
+    }
 
     amq::GenArgs ga;
     memset(&ga, 0, sizeof ga);
@@ -374,7 +402,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     ga.rows = (uint64_t *)(ws + L.off_part);
     ga.rows_n = amq::rows_words(plan.G, b.degree);
     ProfRec *pr = nullptr;
-    if (g_prof.on) {
+    if (g_prof.on && !noalloc_sched) {
         int prc = prof_slot(&pr);
         if (prc) return prc;
         HIP_TRY(hipEventRecord(pr->e[0], stream));
@@ -404,9 +432,10 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     hipError_t e;
     {
         std::lock_guard<std::mutex> lk(st->persist_mu);
-        if (!st->persist_done)
+        if (!st->persist_done) {
+            if (noalloc_sched) return fail(AM_EINVAL, "am_init has not run on this device");
             HIP_TRY(hipEventCreateWithFlags(&st->persist_done, hipEventDisableTiming));
-        else if (st->persist_stream != stream)
+        } else if (st->persist_stream != stream)
             HIP_TRY(hipStreamWaitEvent(stream, st->persist_done, 0));
         e = amq::launch_sweep(sa, fp64, plan.wg, plan.ppt, stream);
         if (e == hipSuccess) {
@@ -554,6 +583,86 @@ int am_price_american(const am_params *params, int64_t n_paths, int32_t n_dates,
     if (rc) return rc;
     *price = out[0];
     *std_err = out[1];
+    return AM_OK;
+}
+
+int am_init(void)
+{
+    DevState *st = nullptr;
+    int rc = get_state(&st);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(st->persist_mu);
+        if (!st->persist_done)
+            HIP_TRY(hipEventCreateWithFlags(&st->persist_done, hipEventDisableTiming));
+    }
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        if (!st->scratch) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(AM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            st->scratch = (char *)ptr;
+        }
+    }
+    // load every single-option kernel's code now: the occupancy queries and
+    // attribute reads make the runtime load each module on this device
+    HIP_TRY(amq::preload_generate());
+    for (int fp64 = 0; fp64 < 2; ++fp64) {
+        const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
+        const int n_tiles = fp64 ? kNTiles64 : kNTiles32;
+        for (int i = 0; i < n_tiles; ++i)
+            for (int d = 0; d < 2 * (AM_MAX_DEGREE + 1); ++d)
+                (void)groups_per_cu(st, fp64, d & 1, tiles[i].wg, tiles[i].ppt, d >> 1);
+    }
+    return AM_OK;
+}
+
+int am_price_american_noalloc(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                              int32_t dtype, void *hip_stream, double *h_out)
+{
+    if (!h_out) return fail(AM_EINVAL, "h_out must be non-NULL");
+    int rc = validate(params, n_paths, n_dates, basis, dtype);
+    if (rc) return rc;
+    dtype = storage_of(n_paths, dtype);
+    const Layout L = make_layout(n_paths, n_dates, dtype);
+    // the bridge schedule follows the workspace regions (L.total is 256-aligned)
+    const size_t sched_bytes = sizeof(amq::BridgeNode) * (size_t)n_dates;
+    const size_t need = L.total + sched_bytes;
+    if (need > (size_t)AM_SCRATCH_BYTES)
+        return fail(AM_EWORKSPACE, "%lld paths x %d dates need %zu bytes; the allocation-free entry point "
+                    "has %zu", (long long)n_paths, n_dates, need, (size_t)AM_SCRATCH_BYTES);
+    DevState *st = find_state();
+    if (!st || !st->scratch) return fail(AM_EINVAL, "am_init has not run on this device");
+    const std::vector<amq::BridgeNode> *hs = nullptr;
+    {
+        // host copies only (built once per date count, kept for the process)
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->host_sched.find(n_dates);
+        if (it == st->host_sched.end()) {
+            std::vector<amq::BridgeNode> h = make_schedule(n_dates);
+            if ((int)h.size() != n_dates || max_slot(h) >= amq::kAnchorSlot)
+                return fail(AM_EDIM, "bridge schedule for %d dates does not fit the register window", n_dates);
+            it = st->host_sched.emplace(n_dates, std::move(h)).first;
+        }
+        hs = &it->second;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    char *ws = st->scratch;
+    amq::BridgeNode *d_sched = (amq::BridgeNode *)(ws + L.total);
+    HIP_TRY(hipMemcpyAsync(d_sched, hs->data(), sched_bytes, hipMemcpyHostToDevice, stream));
+    rc = enqueue(st, params, n_paths, n_dates, basis, dtype, ws, L, stream, -1, 0, d_sched);
+    if (rc) return rc;
+    // result words and the barrier block's first line, into host stack memory
+    double res[16];
+    HIP_TRY(hipMemcpyAsync(res, ws + L.off_result, sizeof res, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const uint32_t *sync = (const uint32_t *)(res + 8);
+    if (sync[2] != 0u) return fail(AM_ETIMEOUT, "a device-side barrier wait ran out (spin limit)");
+    if (!isfinite(res[0]) || !isfinite(res[1])) return fail(AM_EDEVICE, "non-finite result");
+    h_out[0] = res[0];
+    h_out[1] = res[1];
     return AM_OK;
 }
 

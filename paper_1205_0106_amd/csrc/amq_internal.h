@@ -150,6 +150,8 @@ struct BatchGlobal {
 
 // Launchers (defined with the kernels).
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s);
+// Load the single-option generation kernels on the current device.
+hipError_t preload_generate();
 // Single-option sweep with wg (256 or 512) threads per group.  Returns
 // hipErrorInvalidValue if no kernel exists for (fp64, a.laguerre, wg, ppt,
 // a.degree).

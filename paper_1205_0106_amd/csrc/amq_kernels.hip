@@ -502,6 +502,17 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
     return hipGetLastError();
 }
 
+// Make the runtime load the generation kernels' code on the current device
+// now rather than at their first launch (a first use allocates device memory
+// for the code).
+hipError_t preload_generate()
+{
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<float, 0, false>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<double, 0, false>));
+    return e;
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over (precision, basis kind, paths per thread, degree).
 // ---------------------------------------------------------------------------
