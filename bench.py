@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: QMC least-squares American pricing throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--dtype fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--dtype fp32]
 
 A step is one full pricing call (Sobol -> inverse normal -> bridge -> GBM
 paths -> backward induction -> discounted mean) on the configuration's inputs,
@@ -10,9 +10,12 @@ enqueued through the C-ABI on one stream with a torch-owned workspace.  Inputs
 the timed region except the 16-byte result of the last step.  Prints one JSON
 line.
 
-Default workload: the single American put S0=K=100, r=0.05, sigma=0.3, T=1,
-100 dates, 2^20 Sobol paths, weighted Laguerre degree 3, FP32 bulk with FP64
-solve (the FP64 run of the same workload is reported beside it).
+Default workload: the large single American put S0=100, K=110, r=0.03,
+sigma=0.25, T=2, 252 dates, 2^24 Sobol paths, monomials of degree 4, FP32 bulk
+with FP64 solve (the largest single-GPU configuration).  Beside it, as extra
+keys: the 2^20-path, 100-date weighted-Laguerre put in FP32 bulk and FP64; the
+1024-option batch in FP32 bulk against the plain FP64 single-option path over
+the same options; a short serving replay (p50/p99).
 """
 from __future__ import annotations
 
@@ -96,10 +99,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4])
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 4])
     ap.add_argument("--dtype", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-side", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the main workload only (no second workload, batch or serving keys)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving replay reported beside the main line")
+    ap.add_argument("--paper-table2", action="store_true",
+                    help="the paper's Table 2 shape: ten exercise points, 10 .. 10^6 paths, GPU and oracle")
     ap.add_argument("--serve", type=float, default=0.0, metavar="SECONDS",
                     help="serving mode: replay Poisson arrivals (200 req/s) for SECONDS")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
@@ -305,6 +314,109 @@ def cpu_baseline(w):
                 price_on_sample=r.price)
 
 
+def single_run(amq, pricer, w, dtype, steps, warmup):
+    """Time `steps` pricing calls of workload w; price and its distance from
+    the committed oracle value of the same workload."""
+    p = amq.make_params(**w.params(), is_call=w.is_call, allow_exercise=w.allow_exercise)
+    b = amq.make_basis(*w.basis)
+    m = time_steps(amq, pricer, p, b, w, dtype, steps, warmup)
+    m["value"] = w.n_paths * w.n_dates * steps / m["seconds"]
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{w.name.split('_')[0]}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        m["oracle_price"] = g["price"]
+        m["abs_err_vs_oracle"] = abs(m["price"] - g["price"])
+    return m
+
+
+def batch_vs_single(n, steps, warmup):
+    """The batched FP32-bulk form against the plain FP64 single-option path on
+    the same n options: path-steps/s of each (back-to-back calls on one
+    stream between device syncs), and the largest price difference between
+    the two (the FP64 single-option prices match the FP64 oracle to 1e-4)."""
+    import numpy as np
+    import torch
+    import paper_1205_0106_amd as amq
+    from paper_1205_0106_amd.workloads import batch_options
+    specs = batch_options(n)
+    opts = amq.make_options(specs)
+    b = amq.make_basis("monomial", 2)
+    total = sum(d["n_paths"] * d["n_dates"] for d in specs)
+    pr = amq.Pricer(0)
+    for _ in range(warmup):
+        pr.price_batch(opts, b, "fp32", wait=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pr.price_batch(opts, b, "fp32", wait=False)
+    torch.cuda.synchronize()
+    dt32 = (time.perf_counter() - t0) / steps
+    p32 = pr.price_batch(opts, b, "fp32")
+    pr.ws = None
+    torch.cuda.empty_cache()
+    one = amq.Pricer(0)
+    params = [amq.make_params(d["S0"], d["K"], d["r"], d["sigma"], d["T"], d["is_call"]) for d in specs]
+    one.workspace(max(amq.am_workspace_bytes(d["n_paths"], d["n_dates"], b, "fp64") for d in specs))
+    for i in range(min(n, 8)):
+        one.price(params[i], specs[i]["n_paths"], specs[i]["n_dates"], b, "fp64", wait=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, d in enumerate(specs):
+        one.price(params[i], d["n_paths"], d["n_dates"], b, "fp64", wait=False)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    p64 = np.array([one.price(params[i], d["n_paths"], d["n_dates"], b, "fp64") for i, d in enumerate(specs)])
+    one.ws = None
+    torch.cuda.empty_cache()
+    diff = np.abs(p32[:, 0] - p64[:, 0])
+    return {"workload": f"batch of {n} options: put/call 50/50, K U(80,120), S0 100, sigma U(0.1,0.5), "
+                        "r U(0,0.08), T U(0.25,2), dates U{16..256}, paths 2^14-2^18 log-uniform, "
+                        "monomials degree 2",
+            "path_steps": total,
+            "batch_fp32_bulk": {"value": total / dt32, "ms_per_batch": 1e3 * dt32},
+            "single_option_fp64": {"value": total / dt64, "ms_for_all": 1e3 * dt64},
+            "speedup": dt64 / dt32,
+            "max_abs_price_diff": float(diff.max()), "median_abs_price_diff": float(np.median(diff)),
+            "median_naive_std_err": float(np.median(p64[:, 1])),
+            "unit": "path-steps/s"}
+
+
+def paper_table2(steps):
+    """The paper's Table 2 shape (ten exercise points, 10 .. 10^6 paths) on
+    config 1's option: GPU (FP64, whole call between device syncs) and the
+    oracle (one thread), milliseconds per pricing at each path count."""
+    import torch
+    import oracle
+    import paper_1205_0106_amd as amq
+    from paper_1205_0106_amd.workloads import CONFIG1, PAPER_TABLE2_PATHS
+    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    w = CONFIG1
+    M = 10
+    p = amq.make_params(**w.params())
+    b = amq.make_basis(*w.basis)
+    pr = amq.Pricer(0)
+    rows = []
+    for N in PAPER_TABLE2_PATHS:
+        for _ in range(2):
+            pr.price(p, N, M, b, "fp64", wait=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pr.price(p, N, M, b, "fp64", wait=False)
+        torch.cuda.synchronize()
+        gpu_ms = 1e3 * (time.perf_counter() - t0) / steps
+        price = pr.price(p, N, M, b, "fp64")[0]
+        t0 = time.perf_counter()
+        r = oracle.price_american(**w.params(), N=N, M=M, kind=oracle.MONOMIAL, degree=w.basis[1])
+        cpu_ms = 1e3 * (time.perf_counter() - t0)
+        rows.append({"paths": N, "gpu_ms": round(gpu_ms, 4), "oracle_ms": round(cpu_ms, 3),
+                     "gpu_price": price, "oracle_price": r.price, "abs_diff": abs(price - r.price)})
+    return {"metric": "milliseconds per pricing (the paper's Table 2 shape)",
+            "config": {"workload": "put S0 36, K 40, r 0.06, sigma 0.2, T 1, ten exercise dates, "
+                                   "monomials degree 2, FP64"},
+            "oracle": f"single thread, {cpu_model()}", "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -323,19 +435,18 @@ def main():
     if args.paper_estimator or args.rqmc:
         print(json.dumps(variant_run(args)), flush=True)
         return
+    if args.paper_table2:
+        print(json.dumps(paper_table2(max(3, args.steps // 4))), flush=True)
+        return
     import torch
     import paper_1205_0106_amd as amq
-    from paper_1205_0106_amd.workloads import CONFIGS
+    from paper_1205_0106_amd.workloads import CONFIG2, CONFIGS
 
     w = CONFIGS[args.config]
     dtype = args.dtype or ("fp32" if "fp32" in w.dtypes else "fp64")
-    p = amq.make_params(**w.params(), is_call=w.is_call, allow_exercise=w.allow_exercise)
-    b = amq.make_basis(*w.basis)
     pricer = amq.Pricer(0)
     path_steps = w.n_paths * w.n_dates
-
-    m = time_steps(amq, pricer, p, b, w, dtype, args.steps, args.warmup)
-    value = path_steps * args.steps / m["seconds"]
+    m = single_run(amq, pricer, w, dtype, args.steps, args.warmup)
     s = 4 if dtype == "fp32" else 8
 
     # dominant kernel and its roofline (algorithmic bytes: generation writes
@@ -350,10 +461,17 @@ def main():
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic(args.config, dtype, dom), "traffic_unit": "HBM bytes per launch",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(ms, 4)}
+    # the other kernel against the same roofline
+    other = "generate" if dom == "sweep" else "sweep"
+    oms = m["gen_ms"] if other == "generate" else m["sweep_ms"]
+    roofline_other = {"kernel": other, "bound": "hbm", "achieved": round(alg_bytes / (oms * 1e-3) / 1e9, 1),
+                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": round(alg_bytes / (oms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                      "traffic": measured_traffic(args.config, dtype, other), "avg_launch_ms": round(oms, 4)}
 
     out = {
         "metric": "path-steps/s for QMC-LSM American pricing",
-        "value": value,
+        "value": m["value"],
         "unit": "path-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -362,9 +480,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        # arithmetic type of the path: binary64 in both modes (FP32 bulk
-        # stores path values and cashflows in binary32, see config.storage)
-        "dtype": "f64",
+        # arithmetic of the path: FP32 bulk computes the inverse normal in
+        # binary32 and everything after it in binary64 (path values and
+        # cashflows stored in binary32); FP64 is binary64 throughout
+        "dtype": "f32+f64" if dtype == "fp32" else "f64",
         "data": "synthetic (on-device Sobol paths)",
         "config": {"workload": w.name, "n_paths": w.n_paths, "n_dates": w.n_dates,
                    "basis": f"{w.basis[0]} degree {w.basis[1]}",
@@ -374,23 +493,42 @@ def main():
                    if dtype == "fp32" else "FP64 throughout",
                    "S0": w.S0, "K": w.K, "r": w.r, "sigma": w.sigma, "T": w.T},
         "roofline": roofline,
+        "roofline_other_kernel": roofline_other,
         "valu_issue": valu_issue(args.config, dtype, {"generate": m["gen_ms"], "sweep": m["sweep_ms"]}),
         "phase_ms": {"generate": round(m["gen_ms"], 4), "sweep": round(m["sweep_ms"], 4)},
         "price": m["price"],
         "std_err": m["std_err"],
     }
-    gold = os.path.join(ROOT, "tests", "golden", f"oracle_config{args.config}.json")
-    if os.path.exists(gold):
-        g = json.load(open(gold))
-        out["oracle_price"] = g["price"]
-        out["abs_err_vs_oracle"] = abs(m["price"] - g["price"])
+    for k in ("oracle_price", "abs_err_vs_oracle"):
+        if k in m:
+            out[k] = m[k]
     if dtype == "fp32" and "fp64" in w.dtypes and not args.no_fp64_side:
-        m64 = time_steps(amq, pricer, p, b, w, "fp64", max(3, args.steps // 4), 1)
-        out["fp64_side"] = {"value": path_steps * max(3, args.steps // 4) / m64["seconds"],
-                            "price": m64["price"], "phase_ms": {"generate": round(m64["gen_ms"], 4),
-                                                               "sweep": round(m64["sweep_ms"], 4)}}
-        if "oracle_price" in out:
-            out["fp64_side"]["abs_err_vs_oracle"] = abs(m64["price"] - out["oracle_price"])
+        n64 = max(3, args.steps // 4)
+        m64 = single_run(amq, pricer, w, "fp64", n64, 1)
+        out["fp64_side"] = {"value": m64["value"], "price": m64["price"],
+                            "phase_ms": {"generate": round(m64["gen_ms"], 4), "sweep": round(m64["sweep_ms"], 4)},
+                            "abs_err_vs_oracle": m64.get("abs_err_vs_oracle")}
+    pricer.ws = None
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        if w is not CONFIG2:
+            w2 = CONFIG2
+            extra = {"workload": w2.name}
+            for d2 in ("fp32", "fp64"):
+                m2 = single_run(amq, pricer, w2, d2, args.steps, args.warmup)
+                extra[d2] = {"value": m2["value"], "ms_per_step": 1e3 * m2["seconds"] / args.steps,
+                             "phase_ms": {"generate": round(m2["gen_ms"], 4), "sweep": round(m2["sweep_ms"], 4)},
+                             "price": m2["price"], "abs_err_vs_oracle": m2.get("abs_err_vs_oracle")}
+            out["config2"] = extra
+            pricer.ws = None
+            torch.cuda.empty_cache()
+        out["batch_fp32_vs_single_fp64"] = batch_vs_single(1024, max(3, args.steps // 4), 1)
+        if args.serve_seconds > 0:
+            sv = serve(args.serve_seconds, "fp32")
+            out["serving"] = {k: sv[k] for k in ("value", "unit", "p50_ms", "p99_ms", "mean_ms", "completed_ok",
+                                                 "batches", "offered_path_steps_per_s")}
+            out["serving"]["workload"] = sv["config"]["workload"]
+            out["serving"]["requests"] = sv["config"]["requests"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     out["gpu"] = torch.cuda.get_device_name(0)

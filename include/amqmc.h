@@ -374,6 +374,14 @@ void am_debug_set_batch_ppt(int32_t ppt);
  * rounding level). */
 void am_debug_set_sweep_wide(int32_t allow);
 
+/* Test hook: single-option sweeps on this thread use the tile of wg threads
+ * per group and ppt paths per thread (one of the built tiles, e.g. binary32
+ * 512 x 64 or 512 x 128, the slab-resident monomial forms), or fail with
+ * AM_EDIM where it does not apply (row padding, residency); wg = 0 restores
+ * the cost model's choice.  The tile changes the reduction order
+ * (differences at rounding level). */
+void am_debug_set_sweep_tile(int32_t wg, int32_t ppt);
+
 /* Test hook: bound the device-side barrier waits of subsequent calls on this
  * thread to `spins` polls (0 restores the default).  A wait that runs out
  * makes the call return AM_ETIMEOUT after every workgroup has exited. */

@@ -156,6 +156,8 @@ def lib():
         L.am_debug_set_batch_ppt.restype = None
         L.am_debug_set_sweep_wide.argtypes = [i32]
         L.am_debug_set_sweep_wide.restype = None
+        L.am_debug_set_sweep_tile.argtypes = [i32, i32]
+        L.am_debug_set_sweep_tile.restype = None
         L.am_last_error.argtypes = []
         L.am_last_error.restype = ctypes.c_char_p
         L.am_max_dates.argtypes = []
@@ -429,6 +431,11 @@ def am_debug_set_batch_ppt(ppt: int) -> None:
 
 def am_debug_set_sweep_wide(allow: bool) -> None:
     lib().am_debug_set_sweep_wide(1 if allow else 0)
+
+
+def am_debug_set_sweep_tile(wg: int, ppt: int) -> None:
+    """Force the single-option sweep tile on this thread (wg=0: automatic)."""
+    lib().am_debug_set_sweep_tile(int(wg), int(ppt))
 
 
 def am_last_error() -> str:

@@ -265,6 +265,7 @@ const TileShape kTiles32[] = {{512, 4}, {256, 4}, {512, 8}, {256, 16}, {512, 64}
 const TileShape kTiles64[] = {{512, 2}, {256, 2}, {512, 4}, {256, 8}, {512, 8}, {256, 16}, {256, 64}};
 const int kNTiles32 = 8, kNTiles64 = 7;
 thread_local int32_t g_sweep_wide = 1;   // 0: single-option sweeps use 256-thread groups only
+thread_local int32_t g_tile_wg = 0, g_tile_ppt = 0;   // a forced single-option tile (0: the cost model's)
 
 // Tile choice for one sweep.  Every date costs one device-wide sum, whose
 // latency grows with the group count G (every group reads every group's
@@ -280,6 +281,7 @@ int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Pla
     for (int i = 0; i < n_tiles; ++i) {
         const int wg = tiles[i].wg, ppt = tiles[i].ppt;
         if (wg != amq::kWG && !g_sweep_wide) continue;
+        if (g_tile_wg && (wg != g_tile_wg || ppt != g_tile_ppt)) continue;
         const int per_cu = groups_per_cu(st, fp64, laguerre, wg, ppt, degree);
         if (per_cu <= 0) continue;
         int64_t gmax = (int64_t)per_cu * st->num_cu;
@@ -1132,6 +1134,12 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }
 
 void am_debug_set_sweep_wide(int32_t allow) { g_sweep_wide = allow ? 1 : 0; }
+
+void am_debug_set_sweep_tile(int32_t wg, int32_t ppt)
+{
+    g_tile_wg = wg > 0 ? wg : 0;
+    g_tile_ppt = wg > 0 ? ppt : 0;
+}
 
 int am_batch_autotune(const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
                       void *d_workspace, size_t ws_bytes, void *hip_stream, int32_t *best_ppt,

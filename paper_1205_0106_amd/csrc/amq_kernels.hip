@@ -571,7 +571,9 @@ static size_t one_per_cu_lds(int dev, const void *f)
 hipError_t launch_sweep(const SweepArgs &a, int fp64, int wg, int ppt, hipStream_t s)
 {
     if (wg != kWG && wg != 512) return hipErrorInvalidValue;
-    const void *f = sweep_lookup(fp64, a.laguerre, ppt, a.degree, wg == 512 ? 2 : 0);
+    // slab-resident tiles come in a call form (kind 3) and a put form (kind 2)
+    const void *f = (wg == 512 && a.is_call) ? sweep_lookup(fp64, a.laguerre, ppt, a.degree, 3) : nullptr;
+    if (!f) f = sweep_lookup(fp64, a.laguerre, ppt, a.degree, wg == 512 ? 2 : 0);
     if (!f) return hipErrorInvalidValue;
     SweepArgs args = a;
     const void *Sp = a.S;

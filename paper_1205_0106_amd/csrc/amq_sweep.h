@@ -19,13 +19,13 @@ namespace amq {
 // p), [8] solved flag, [9] in-the-money count.  Branch-free (a rejected
 // pivot takes the square root of 1 and clears the flag), so the independent
 // square roots of the equilibration overlap.
-template <int D>
-__device__ __forceinline__ void solve_date(const double *tot, double *beta, double (*L)[8], double *w)
+template <int D, typename TT = const double *, typename LT = double (*)[8], typename WT = double *>
+__device__ __forceinline__ void solve_date(TT tot, double *beta, LT L, WT w)
 {
     constexpr int P = D + 1, NA = 2 * D + 1;
     const double n = rint(tot[NA + P]);
     bool ok = n >= (double)P;
-    double *sc = w, *rl = w + 8, *y = w + 16, *gam = w + 24;
+    WT sc = w, rl = w + 8, y = w + 16, gam = w + 24;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const double d = tot[2 * i];
@@ -107,13 +107,29 @@ struct SweepShape {
     static constexpr int waves() { return (sizeof(T) * PPT <= 16 && !LAG && D <= 2) ? 4 : 2; }
 };
 
+// Slab-resident tiles (binary32 path values, monomial basis, one group of
+// 512 threads per CU, 64 or 128 paths per thread): a date's slab stays on
+// chip between the moment pass and the exercise update, the first NKL
+// vectors of each thread in LDS and the next NKR in registers; the last NRR
+// (what neither holds next to the resident cashflows) are read again for the
+// update.
+template <typename T, int PPT, int WG, bool LAG>
+struct Resident {
+    static constexpr bool on = sizeof(T) == 4 && WG == 512 && !LAG && (PPT == 64 || PPT == 128);
+    static constexpr int NVEC = PPT * (int)sizeof(T) / 16;
+    static constexpr int NKL = NVEC < 19 ? NVEC : 19;   // at most 19 x 512 x 16 B = 152 KiB of LDS
+    static constexpr int NKR = NVEC - NKL < 8 ? NVEC - NKL : 8;
+    static constexpr int NRR = NVEC - NKL - NKR;
+};
+
 // Vectors of a streamed tile's date slab kept in LDS between the moment pass
 // and the exercise update (one group of 512 threads per CU: up to 128 KiB),
 // so the update reads only the rest from memory again.
-template <typename T, int PPT, int WG>
+template <typename T, int PPT, int WG, bool LAG = false>
 constexpr int stream_keep_vecs()
 {
     if (SweepShape<T, PPT>::KEEP || WG != 512) return 0;
+    if (Resident<T, PPT, WG, LAG>::on) return 0;   // their LDS slots are arrays of their own
     constexpr int cap = (128 * 1024) / (WG * 16);
     return SweepShape<T, PPT>::NVEC < cap ? SweepShape<T, PPT>::NVEC : cap;
 }
@@ -306,14 +322,16 @@ __device__ __forceinline__ void sweep_terminal(const SweepArgs &a, const T *__re
 // The solve of date k by thread 0 (registers where the kernel has room,
 // else LDS), and group 0's date record: coefficients, flag and count, the
 // moments, and device clock stamps of the date's phases.
-template <int D, bool REGS>
+// MODE 0: totals and factor in registers; 1: factor in LDS (the compiler may
+// still keep it in registers).
+template <int D, int MODE>
 __device__ __forceinline__ void solve_and_record(const SweepArgs &a, uint32_t gid, int k, const double *s_tot,
                                                  double *s_beta, double (*s_L)[8], double *s_w,
                                                  const uint64_t (&stamp)[3])
 {
     constexpr int NV = 3 * D + 4;
     const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
-    if constexpr (REGS) {
+    if constexpr (MODE == 0) {
         // the totals in registers first: every LDS read issued at once
         double tr[NV], Lr[8][8], wr[32];
 #pragma unroll
@@ -333,6 +351,109 @@ __device__ __forceinline__ void solve_and_record(const SweepArgs &a, uint32_t gi
         rec[kRecTime + 2] = (double)__builtin_amdgcn_s_memrealtime();     // solved
         rec[kRecTime + 3] = (double)stamp[1];                             // next date's Gram part summed
         rec[kRecTime + 4] = (double)stamp[2];                             // date's pass started
+    }
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// The same solve as solve_date (equilibration by the diagonal, Cholesky with
+// pivots at or below 1e-14 rejected, forward and backward substitution) by
+// the 64 lanes of one wave: lane i < P holds row i of the equilibrated
+// matrix and of its factor, rows cross lanes through readlane, and the
+// factor's columns through LDS for the backward substitution.  A few
+// registers per lane instead of the whole factor in one thread's registers,
+// for kernels whose register file holds resident path data.  Lanes past P
+// mirror row P-1 (their values are not used).  tot: LDS; beta: LDS
+// [0..7] coefficients (zero past P, all zero if rejected), [8] solved flag,
+// [9] count; s_col: LDS [8][8] scratch.  Call with every lane of the wave.
+template <int D>
+__device__ __forceinline__ void solve_date_wave(const double *tot, double *beta, double (*s_col)[8])
+{
+    constexpr int P = D + 1, NA = 2 * D + 1;
+    const int lane = threadIdx.x & 63;
+    const int i = lane < P ? lane : P - 1;
+    const double n = rint(tot[NA + P]);
+    const double dii = tot[2 * i];
+    const double sci = rsqrt_f64(dii > 0.0 ? dii : 1.0);
+    bool ok = n >= (double)P && __builtin_amdgcn_ballot_w64(lane < P && !(dii > 0.0)) == 0;
+    double a[P], L[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        a[j] = tot[i + j] * sci * readlane_f64(sci, j);
+        L[j] = 0.0;
+    }
+    // Cholesky, column j: lane j's pivot, then every lane's entry of column j
+    double rli = 1.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        double d = a[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) d -= L[l] * L[l];
+        const double dj = readlane_f64(d, j);
+        ok = ok && dj > 1e-14;
+        const double rlj = rsqrt_f64(dj > 1e-14 ? dj : 1.0);
+        rli = lane == j ? rlj : rli;
+        double e = a[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) e -= L[l] * readlane_f64(L[l], j);
+        L[j] = e * rlj;
+    }
+    // forward substitution: y_l leaves lane l once its sum is complete
+    double t = tot[NA + i] * sci, yi = 0.0;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        const double yl = readlane_f64(t * rli, l);
+        yi = lane == l ? yl : yi;
+        t -= L[l] * yl;
+    }
+    // backward substitution with the factor's columns: lane i reads column i
+    if (lane < P) {
+#pragma unroll
+        for (int l = 0; l < P; ++l) s_col[i][l] = L[l];
+    }
+    __builtin_amdgcn_wave_barrier();
+    double Lc[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) Lc[l] = s_col[l][i];
+    double u = yi, gi = 0.0;
+#pragma unroll
+    for (int l = P - 1; l >= 0; --l) {
+        const double gl = readlane_f64(u * rli, l);
+        gi = lane == l ? gl : gi;
+        u -= Lc[l] * gl;
+    }
+    if (lane < 8) beta[lane] = (lane < P && ok) ? gi * sci : 0.0;
+    if (lane == 0) {
+        beta[8] = ok ? 1.0 : 0.0;
+        beta[9] = n;
+    }
+}
+
+// The wave-parallel solve of date k by wave 0 and group 0's date record, as
+// solve_and_record.  Call with every lane of wave 0.
+template <int D>
+__device__ __forceinline__ void solve_and_record_wave(const SweepArgs &a, uint32_t gid, int k, const double *s_tot,
+                                                      double *s_beta, double (*s_col)[8], const uint64_t (&stamp)[3])
+{
+    constexpr int NV = 3 * D + 4;
+    const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
+    solve_date_wave<D>(s_tot, s_beta, s_col);
+    if (gid == 0 && threadIdx.x == 0) {
+        double *rec = a.rec + (size_t)k * kRec;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) rec[q] = s_beta[q];
+        for (int q = 0; q < NV && q < 22; ++q) rec[10 + q] = s_tot[q];
+        rec[kRecTime + 0] = (double)stamp[0];
+        rec[kRecTime + 1] = (double)c_all;
+        rec[kRecTime + 2] = (double)__builtin_amdgcn_s_memrealtime();
+        rec[kRecTime + 3] = (double)stamp[1];
+        rec[kRecTime + 4] = (double)stamp[2];
     }
 }
 
@@ -516,7 +637,7 @@ __device__ __forceinline__ void sweep_keep(const SweepArgs &a, const T *__restri
             alive = false;
             return;
         }
-        if (tid == 0) solve_and_record<D, true>(a, gid, k, s_tot, s_beta, nullptr, nullptr, stamp);
+        if (tid == 0) solve_and_record<D, 0>(a, gid, k, s_tot, s_beta, nullptr, nullptr, stamp);
         __syncthreads();
 
         if (s_beta[8] != 0.0) {
@@ -551,7 +672,7 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
                                              double (*s_red)[32], double *s_tot, double *s_beta, double (*s_L)[8],
                                              double *s_w, DateConst *s_dc, Vec<T> *s_keep, int *s_flag)
 {
-    constexpr int NK = stream_keep_vecs<T, PPT, WG>();
+    constexpr int NK = stream_keep_vecs<T, PPT, WG, LAG>();
     using SH = SweepShape<T, PPT>;
     constexpr int VW = SH::VW, NVEC = SH::NVEC, PD = SH::PD;
     constexpr int NA = 2 * D + 1, NB = D + 1, P = D + 1;
@@ -606,7 +727,7 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
             alive = false;
             return;
         }
-        if (tid == 0) solve_and_record<D, false>(a, gid, k, s_tot, s_beta, s_L, s_w, stamp);
+        if (tid == 0) solve_and_record<D, 1>(a, gid, k, s_tot, s_beta, s_L, s_w, stamp);
         __syncthreads();
 
         if (s_beta[8] != 0.0) {
@@ -642,6 +763,306 @@ __device__ __forceinline__ void sweep_stream(const SweepArgs &a, const T *__rest
     }
 }
 
+// Strike as a binary32 threshold on the stored path values: for binary32 s
+// and binary64 K, s > K exactly when s > K rounded down (call) and s < K
+// exactly when s < K rounded up (put).  (The row padding holds these values,
+// so padded paths are never in the money.)
+template <bool CALL>
+__device__ __forceinline__ float strike_threshold_f32(double K)
+{
+    float k = (float)K;
+    if (CALL && (double)k > K) k = __int_as_float(__float_as_int(k) - 1);
+    if (!CALL && (double)k < K) k = __int_as_float(__float_as_int(k) + 1);
+    return k;
+}
+
+// Monomial moments of one path for the slab-resident tile.  With m = 1 on
+// an in-the-money path (else 0) and y = m xs, the powers y^q (q <= D) come by
+// squaring (D - 1 multiplies); the Gram sums of y^q for q = 1..D add them and
+// those for q = D+1..2D are one fma y^D y^(q-D) each; the right-hand side is
+// one fma pv y^q per q (y^0 = m).  A[q-1]: sum of y^q (q = 1..2D); R[q]: sum
+// of pv y^q (q = 0..D).  The count (q = 0) comes from wave ballots.
+template <int D>
+__device__ __forceinline__ void resident_moments(double *A, double *R, double s, double pv, bool itm, double xa,
+                                                 double xb)
+{
+    const double m = itm ? 1.0 : 0.0;
+    double p[D + 1];
+    p[0] = m;
+    if constexpr (D >= 1) p[1] = fma(s, xa, xb) * m;
+#pragma unroll
+    for (int q = 2; q <= D; ++q) p[q] = p[q / 2] * p[q - q / 2];
+#pragma unroll
+    for (int q = 1; q <= D; ++q) A[q - 1] += p[q];
+#pragma unroll
+    for (int q = D + 1; q <= 2 * D; ++q) A[q - 1] = fma(p[D], p[q - D], A[q - 1]);
+#pragma unroll
+    for (int q = 0; q <= D; ++q) R[q] = fma(pv, p[q], R[q]);
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) asm volatile("" : "+v"(A[q]));
+#pragma unroll
+    for (int q = 0; q <= D; ++q) asm volatile("" : "+v"(R[q]));
+}
+
+// Exercise update of one path for the slab-resident tile: the discounted
+// payoff dk sg (s - K) as one fma (dsg = dk sg, dnsk = -dk sg K), the fitted
+// continuation by Horner in xs; exercise when in the money and the
+// discounted payoff exceeds the fit (for an in-the-money path the payoff is
+// positive, so this is the test dk h > max(fit, 0)).
+template <bool CALL, int D>
+__device__ __forceinline__ float resident_update(float s32, float pvj, float kthr, double xa, double xb, double dsg,
+                                                 double dnsk, const double *gam)
+{
+    // recomputed from the stored value: keeping the moment pass's abscissae
+    // and in-the-money masks of every path across the device-wide sum would
+    // take more registers than the kernel has
+    double s = (double)s32;
+    asm volatile("" : "+v"(s));
+    const bool itm = CALL ? s > (double)kthr : s < (double)kthr;
+    const double xs = fma(s, xa, xb);
+    double cont = gam[D];
+#pragma unroll
+    for (int q = D - 1; q >= 0; --q) cont = fma(cont, xs, gam[q]);
+    const double ex = fma(dsg, s, dnsk);
+    return (itm && ex > cont) ? (float)ex : pvj;
+}
+
+// Compile-time loop: f(Ic<B>{}), ..., f(Ic<E-1>{}).
+template <int I> struct Ic { static constexpr int value = I; };
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(Ic<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Wait until at most N vector memory operations of this wave are
+// outstanding (they complete in issue order).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N <= 63, "vmcnt field");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// LDS slots of the slab-resident tile: slot j lives in array j mod 8, at
+// position j / 8 (eight arrays: the compiler tracks direct-to-LDS loads per
+// target array, for at most eight arrays, so the LDS this kernel reads
+// otherwise is never made to wait for them).  The slots themselves are read
+// with read_slot after an explicit wait for their own load.
+template <int A, int NS>
+__device__ __forceinline__ Vec<float> *resident_array()
+{
+    __shared__ Vec<float> s[NS * 512];
+    return s;
+}
+template <int J, int NKL>
+__device__ __forceinline__ Vec<float> *resident_slot()
+{
+    constexpr int A = J % 8;
+    return resident_array<A, (NKL - A + 7) / 8>() + (J / 8) * 512;
+}
+
+// A 16-byte LDS read, complete on return.  The slab-resident tile's LDS
+// slots are filled by direct-to-LDS loads that the tile waits for itself
+// (wait_vmcnt, counting its own requests); reading them outside the
+// compiler's view keeps it from adding a conservative wait for every load
+// in flight before each read.
+__device__ __forceinline__ Vec<float> read_slot(const Vec<float> *base, uint32_t lane_off)
+{
+    using V4 = float __attribute__((ext_vector_type(4)));
+    // the array's LDS address is wave-uniform (a scalar operand), the lane's
+    // byte offset one register shared by every slot
+    const uint32_t b = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base;
+    V4 r;
+    uint32_t t;
+    asm volatile("v_add_u32 %1, %2, %3\n\tds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                 : "=v"(r), "=&v"(t)
+                 : "s"(b), "v"(lane_off));
+    Vec<float> v;
+    v.v[0] = r.x;
+    v.v[1] = r.y;
+    v.v[2] = r.z;
+    v.v[3] = r.w;
+    return v;
+}
+
+// Slab-resident tile: per date, a moment pass over the slab, the
+// device-wide sum and solve, then the exercise update over the same values.
+// A thread's 4-path vectors ("slots", j = 0..NVEC-1) are processed in the
+// same order in both passes: the first NKL live in LDS from their load until
+// the update has read them (loaded straight from memory into LDS, no
+// registers in flight), the next NKR in registers, the last NRR are read
+// again for the update.  Loads run PF slots ahead of their use: the moment
+// pass requests slot j + PF as it reaches slot j, the update requests the
+// re-read slots PF ahead and, over its last PF slots, the first PF slots of
+// the next date (each freed by then), so about PF slots per thread are in
+// flight at any time and no wave stalls on a full memory queue.  Before
+// reading LDS slot j the moment pass waits until at most the requests made
+// after slot j's are outstanding (vector memory operations complete in
+// issue order; operations the compiler adds only make the wait stricter).
+// Date constants come through scalar loads issued a date ahead.
+template <int PPT, int D, bool CALL>
+__device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *__restrict__ S, uint32_t gid,
+                                               const TileIO<float, PPT, 512> &io, float (&pv)[PPT], uint32_t &epoch,
+                                               bool &alive, double (*s_red)[32], double *s_tot, double *s_beta,
+                                               double (*s_L)[8], double *s_w, int *s_flag)
+{
+    constexpr int WG = 512;
+    using RS = Resident<float, PPT, WG, false>;
+    constexpr int NKL = RS::NKL, NKR = RS::NKR, NRR = RS::NRR, NVEC = RS::NVEC;
+    constexpr int PF = NVEC < 12 ? NVEC : 12;
+    constexpr int NA = 2 * D + 1, NB = D + 1;
+    constexpr int NV = NA + NB + 1;
+    constexpr int RW = row_words(D);
+    constexpr uint32_t JS = 64 * 4;          // elements between a lane's vectors
+    const int tid = threadIdx.x;
+    // wave-uniform, so the LDS destinations of the direct loads are scalar
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t ld = a.ld;
+    const int M = a.M;
+    const double sg = CALL ? 1.0 : -1.0, nsk = -sg * a.K;
+    const float kthr = strike_threshold_f32<CALL>(a.K);
+    const uint32_t G = (uint32_t)a.G;
+    if (!(a.allow_exercise && M >= 2)) return;
+
+    // date constants through the scalar cache (written by the generation
+    // kernel, read-only here): scalar registers, and their waits are not
+    // ordered behind the slab's vector loads
+    const __attribute__((address_space(4))) DateConst *dcs =
+        (const __attribute__((address_space(4))) DateConst *)a.datec;
+    struct DC { double disc, xa, xb; };
+    auto dconst = [&](int k) {
+        DC d;
+        d.disc = dcs[k].disc;
+        d.xa = dcs[k].xa;
+        d.xb = dcs[k].xb;
+        return d;
+    };
+    Vec<float> kr[NKR > 0 ? NKR : 1], rr[NRR > 0 ? NRR : 1];
+    const uint32_t lane_off = (uint32_t)tid * 16u;   // this thread's byte offset in an LDS slot
+    // this wave's element offset in an LDS slot, redefined (opaquely) every
+    // date so the direct loads' LDS addresses are formed where they are used
+    // rather than all kept in scalar registers for the whole sweep
+    uint32_t wave_el = (uint32_t)wave * 64u;
+    // request slot j of `row`: this wave's 64 slots of an LDS slot receive
+    // lane l's 16 bytes at +16 l; register and re-read slots load into
+    // their registers
+    auto request = [&](const float *row, auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j < NKL) {
+            __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(row + io.tile0), (short)0, TileIO<float, PPT, WG>::kTileBytes, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (__attribute__((address_space(3))) void *)(resident_slot<j, NKL>() + wave_el), 16, io.voff,
+                (uint32_t)j * JS * 4u, 0, 0);
+        } else if constexpr (j < NKL + NKR) {
+            kr[j - NKL] = io.load(row, j);
+        } else {
+            rr[j - NKL - NKR] = io.load(row, j);
+        }
+    };
+    // slot j's values; in the moment pass an LDS slot first waits for its
+    // load (the compiler's waits cover the register slots)
+    auto slot = [&](auto jc, bool moment) -> Vec<float> {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j < NKL) {
+            if (moment) wait_vmcnt<(PF < NVEC - 1 - j ? PF : NVEC - 1 - j)>();
+            return read_slot(resident_slot<j, NKL>(), lane_off);
+        } else if constexpr (j < NKL + NKR) {
+            return kr[j - NKL];
+        } else {
+            return rr[j - NKL - NKR];
+        }
+    };
+
+    DC dcc = dconst(M - 1);
+    {
+        const float *row = S + (size_t)(M - 2) * ld;
+        static_for<0, PF>([&](auto jc) { request(row, jc); });
+    }
+    for (int k = M - 1; k >= 1; --k) {
+        asm volatile("" : "+s"(wave_el));
+        const double xa = dcc.xa, dk = dcc.disc;
+        // the abscissa offset in vector registers once per date (an fma
+        // takes one scalar operand: xa)
+        double xb = dcc.xb;
+        asm volatile("" : "+v"(xb));
+        const DC dcn = dconst(k >= 2 ? k - 1 : 1);
+        uint64_t stamp[3];
+        stamp[2] = __builtin_amdgcn_s_memrealtime();
+        const float *row = S + (size_t)(k - 1) * ld;
+
+        // moment pass.  tv is the row the device-wide sum takes: [count,
+        // Gram sums q = 1..2D, right-hand side q = 0..D, count]
+        double tv[NV];
+#pragma unroll
+        for (int q = 1; q < NV - 1; ++q) tv[q] = 0.0;
+        double *A = tv + 1, *R = tv + NA;
+        uint32_t cnt = 0;
+        static_for<0, NVEC>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr (j + PF < NVEC) request(row, Ic<j + PF>{});
+            const Vec<float> v = slot(jc, true);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool itm = CALL ? v.v[e] > kthr : v.v[e] < kthr;
+                cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(itm));
+                asm volatile("" : "+s"(cnt));   // one running count, not one register per path
+                resident_moments<D>(A, R, (double)v.v[e], (double)pv[j * 4 + e], itm, xa, xb);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+
+        // the register part as new values for the update, so nothing derived
+        // from them in the moment pass (conversions, masks) is kept for it
+#pragma unroll
+        for (int jj = 0; jj < NKR; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(kr[jj].v[e]));
+        tv[0] = 0.0;
+        tv[NV - 1] = (double)cnt;   // wave-uniform: summed over the waves only
+        group_sum<NV, 1, WG>(tv, s_red);
+        tv[0] = tv[NV - 1];
+        ++epoch;
+        stamp[0] = stamp[1] = __builtin_amdgcn_s_memrealtime();
+        if (!allreduce<NV, RW, WG>(tv, gid, G, a.rows, a.sync, a.err, epoch, a.spin_limit, s_tot, s_red, s_flag)) {
+            alive = false;
+            return;
+        }
+        if (wave == 0) solve_and_record_wave<D>(a, gid, k, s_tot, s_beta, s_L, stamp);
+        __syncthreads();
+
+        // a date that allows no exercise runs the same update with a strike
+        // threshold no path passes (branch-free: no copies of the cashflows)
+        const bool solved = s_beta[8] != 0.0;
+        const float kthr_u = solved ? kthr : (CALL ? __int_as_float(0x7f800000) : __int_as_float(0xff800000));
+        double gam[D + 1];
+#pragma unroll
+        for (int q = 0; q <= D; ++q) gam[q] = uniform_f64(s_beta[q]);
+        const double dsg = dk * sg, dnsk = dk * nsk;
+        // the next date's slab (the last date requests date 1 again, unused)
+        const float *nrow = S + (size_t)(k >= 2 ? k - 2 : 0) * ld;
+        static_for<0, NVEC>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            // the re-read slots again, PF ahead
+            if constexpr (t + PF >= NKL + NKR && t + PF < NVEC) request(row, Ic<t + PF>{});
+            const Vec<float> v = slot(tc, false);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                pv[t * 4 + e] = resident_update<CALL, D>(v.v[e], pv[t * 4 + e], kthr_u, xa, xb, dsg, dnsk, gam);
+            // over the last PF slots, the first PF slots of the next date
+            // (slot t - (NVEC - PF) was read PF slots ago and is free)
+            if constexpr (t >= NVEC - PF) request(nrow, Ic<t - (NVEC - PF)>{});
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        dcc = dcn;
+        __syncthreads();   // s_beta reuse
+    }
+}
+
 // LDS of one sweep workgroup.
 template <typename T, int PPT, bool LAG, int WG>
 struct SweepLds {
@@ -657,14 +1078,16 @@ struct SweepLds {
     // component-major partials of the LDS group sums (512-thread groups):
     // [8][WG]; consecutive sums are separated by barriers
     double x[KEEP && WG == 512 ? 8 * WG : 1];
-    DateConst dc[KEEP ? 1 : kMaxDates + 1];
+    DateConst dc[(KEEP || Resident<T, PPT, WG, LAG>::on) ? 1 : kMaxDates + 1];
     // streamed tiles: the first vectors of each thread's slab, kept from the
     // moment pass for the update ([vector][thread])
-    Vec<T> keep[stream_keep_vecs<T, PPT, WG>() > 0 ? stream_keep_vecs<T, PPT, WG>() * WG : 1];
+    Vec<T> keep[stream_keep_vecs<T, PPT, WG, LAG>() > 0 ? stream_keep_vecs<T, PPT, WG, LAG>() * WG : 1];
     int flag[2 + WG / 64];
 };
 
-template <typename T, int PPT, int D, bool LAG, int WG>
+// SIDE: 1 call, 2 put (slab-resident tiles are compiled per payoff side), 0
+// either (read from the arguments).
+template <typename T, int PPT, int D, bool LAG, int WG, int SIDE = 0>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restrict__ S, uint32_t gid,
                                            uint32_t e0, T (&pv)[PPT], uint32_t &epoch, bool &alive,
                                            SweepLds<T, PPT, LAG, WG> &L)
@@ -674,6 +1097,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
     if constexpr (SweepShape<T, PPT>::KEEP) {
         sweep_keep<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.red2, L.tot, L.beta, L.wl, L.x,
                                        L.flag);
+    } else if constexpr (Resident<T, PPT, WG, LAG>::on) {
+        static_assert(SIDE == 1 || SIDE == 2, "slab-resident tiles are compiled per payoff side");
+        sweep_resident<PPT, D, SIDE == 1>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.flag);
     } else {
         sweep_stream<T, PPT, D, LAG, WG>(a, S, gid, io, pv, epoch, alive, L.red, L.tot, L.beta, L.L, L.w, L.dc,
                                          L.keep, L.flag);
@@ -761,7 +1187,7 @@ __device__ __forceinline__ uint32_t tile_e0(uint32_t gid)
 // WG: threads per group, 256 or (register-resident tiles) 512: two waves
 // of one group per SIMD, so one wave's dependent binary64 latencies and
 // scalar/LDS issue slots overlap the other's vector work.
-template <typename T, int PPT, int D, bool LAG, int WG>
+template <typename T, int PPT, int D, bool LAG, int WG, int SIDE = 0>
 __global__ void __launch_bounds__(WG)
 __attribute__((amdgpu_waves_per_eu(WG == 512 ? 2 : SweepShape<T, PPT>::template waves<D, LAG>())))
 sweep_kernel(SweepArgs a, const T *__restrict__ S)
@@ -774,7 +1200,7 @@ sweep_kernel(SweepArgs a, const T *__restrict__ S)
     T pv[PPT];
     uint32_t epoch = 0;
     bool alive = true;
-    sweep_body<T, PPT, D, LAG, WG>(a, S, gid, e0, pv, epoch, alive, L);
+    sweep_body<T, PPT, D, LAG, WG, SIDE>(a, S, gid, e0, pv, epoch, alive, L);
     if (!alive) return;
     sweep_final<T, PPT, D, WG>(a, gid, e0, pv, epoch, L.red, L.tot, L.flag);
 }
@@ -832,14 +1258,20 @@ sweep_batch_kernel(const BatchOpt *__restrict__ opts, const int32_t *__restrict_
 // Kernel addresses by (paths per thread, degree) for one precision and basis
 // kind; `kind` selects the single-option kernel with 256-thread groups (0),
 // the many-option kernel (1) or the single-option kernel with 512-thread
-// groups (2).  Null where not built.  Each (precision, basis kind) pair is
-// instantiated in its own translation unit.
+// groups (2; for slab-resident tiles the put form), and the call form of a
+// slab-resident tile (3).  Null where not built.  Each (precision, basis
+// kind) pair is instantiated in its own translation unit.
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, int D, bool LAG, int KIND>
 inline const void *sweep_addr()
 {
+    constexpr bool res = Resident<T, PPT, 512, LAG>::on;
     if constexpr (KIND == 1) return (const void *)&sweep_batch_kernel<T, PPT, D, LAG>;
-    else return (const void *)&sweep_kernel<T, PPT, D, LAG, KIND == 2 ? 512 : kWG>;
+    else if constexpr (KIND == 3) {
+        if constexpr (res) return (const void *)&sweep_kernel<T, PPT, D, LAG, 512, 1>;
+        else return nullptr;
+    } else if constexpr (KIND == 2) return (const void *)&sweep_kernel<T, PPT, D, LAG, 512, res ? 2 : 0>;
+    else return (const void *)&sweep_kernel<T, PPT, D, LAG, kWG>;
 }
 
 template <typename T, int PPT, bool LAG, int KIND>
@@ -864,6 +1296,7 @@ template <typename T, bool LAG>
 inline const void *sweep_table(int ppt, int degree, int kind)
 {
     if constexpr (sizeof(T) == 8) {
+        if (kind == 3) return nullptr;   // no slab-resident binary64 tiles
         if (kind == 1) {
             switch (ppt) {
             case 2: return sweep_entry<T, 2, LAG, 1>(degree);
@@ -900,6 +1333,13 @@ inline const void *sweep_table(int ppt, int degree, int kind)
             case 8: return sweep_entry<T, 8, LAG, 2>(degree);
             case 64: return sweep_entry<T, 64, LAG, 2>(degree);
             case 128: return sweep_entry<T, 128, LAG, 2>(degree);
+            default: return nullptr;
+            }
+        }
+        if (kind == 3) {
+            switch (ppt) {
+            case 64: return sweep_entry<T, 64, LAG, 3>(degree);
+            case 128: return sweep_entry<T, 128, LAG, 3>(degree);
             default: return nullptr;
             }
         }

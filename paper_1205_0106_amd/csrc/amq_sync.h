@@ -237,7 +237,10 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
     static_assert(RW == 16 || RW == 32, "row width");
     constexpr int NW = WG / 64;
     constexpr uint32_t RP = WG / RW;    // rows per pass
-    constexpr int KB = 16;              // passes per batch (loads in flight per thread)
+    // passes per batch (loads in flight per thread; 512-thread groups hold
+    // their cashflows and slab values in registers meanwhile).  The order in
+    // which a thread adds its rows does not depend on it.
+    constexpr int KB = WG >= 512 ? 8 : 16;
     const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t it = 0;

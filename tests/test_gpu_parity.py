@@ -259,6 +259,36 @@ def test_group_size_forms_agree(amq, orc, pricer, N, M, basis, dtype):
         assert np.array_equal(out[0][1], od["nitm"][1:M])
 
 
+@pytest.mark.parametrize("ppt,N,M,degree,call,K", [
+    (128, 3 * 65536 - 1234, 24, 4, False, 110.0), (128, 3 * 65536 - 1234, 24, 4, True, 95.0),
+    (128, 2 * 65536 - 5, 13, 6, False, 104.0), (128, 2 * 65536 - 5, 9, 1, True, 100.0),
+    (128, 65536, 7, 0, False, 100.0),
+    (64, 100001, 17, 2, False, 100.3), (64, 100001, 17, 3, True, 97.0), (64, 40000, 30, 5, False, 120.0),
+    (64, 50000, 10, 4, True, 150.0)])
+def test_slab_resident_tiles(amq, orc, pricer, ppt, N, M, degree, call, K):
+    # binary32 monomial tiles of 512 threads x 64 or 128 paths keep each
+    # date's slab on chip between the moment pass and the update (LDS,
+    # registers, and for 128 paths a part read again); forced here at sizes
+    # the oracle prices quickly, puts and calls (separately compiled), all
+    # degrees, dates where too few paths are in the money to fit
+    kw = dict(S0=100.0, K=K, r=0.04, sigma=0.3, T=1.5)
+    ores, od = oracle_price(orc, None, N=N, M=M, basis=("monomial", degree), is_call=call, **kw)
+    try:
+        amq.am_debug_set_sweep_tile(512, ppt)
+        price, se, v = gpu_price(amq, pricer, None, N=N, M=M, dtype="fp32", basis=("monomial", degree),
+                                 is_call=call, **kw)
+    finally:
+        amq.am_debug_set_sweep_tile(0, 0)
+    rec = v["rec"].cpu().numpy()
+    nitm = rec[1:M, 9].astype(np.int64)
+    solved = rec[1:M, 8]
+    log(f"  ppt={ppt} N={N} M={M} d={degree} call={call}: gpu {price:.10f} oracle {ores.price:.10f} "
+        f"skipped {int((solved == 0).sum())}")
+    assert abs(price - ores.price) <= TOL["fp32"]
+    assert np.abs(nitm - od["nitm"][1:M]).max() <= 2
+    assert abs(se - ores.std_err) <= 0.02 * ores.std_err
+
+
 def test_team_level_device_sum(amq, orc, pricer):
     # more than 256 workgroups: teams sum first; 500 groups of 64 paths per
     # thread leaves a last team of 4 (teams of 16)
