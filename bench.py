@@ -316,7 +316,8 @@ def cpu_baseline(w):
 
 def single_run(amq, pricer, w, dtype, steps, warmup):
     """Time `steps` pricing calls of workload w; price and its distance from
-    the committed oracle value of the same workload."""
+    the committed oracle value of the same workload (FP32 bulk: the oracle on
+    binary32-stored paths, and the all-binary64 oracle beside it)."""
     p = amq.make_params(**w.params(), is_call=w.is_call, allow_exercise=w.allow_exercise)
     b = amq.make_basis(*w.basis)
     m = time_steps(amq, pricer, p, b, w, dtype, steps, warmup)
@@ -324,8 +325,12 @@ def single_run(amq, pricer, w, dtype, steps, warmup):
     gold = os.path.join(ROOT, "tests", "golden", f"oracle_{w.name.split('_')[0]}.json")
     if os.path.exists(gold):
         g = json.load(open(gold))
-        m["oracle_price"] = g["price"]
-        m["abs_err_vs_oracle"] = abs(m["price"] - g["price"])
+        ref = g
+        if dtype == "fp32" and w.n_paths >= amq.AM_FP32_MIN_PATHS and "store32" in g:
+            ref = g["store32"]
+            m["abs_err_vs_binary64_oracle"] = abs(m["price"] - g["price"])
+        m["oracle_price"] = ref["price"]
+        m["abs_err_vs_oracle"] = abs(m["price"] - ref["price"])
     return m
 
 
@@ -333,7 +338,9 @@ def batch_vs_single(n, steps, warmup):
     """The batched FP32-bulk form against the plain FP64 single-option path on
     the same n options: path-steps/s of each (back-to-back calls on one
     stream between device syncs), and the largest price difference between
-    the two (the FP64 single-option prices match the FP64 oracle to 1e-4)."""
+    the two (the FP64 single-option prices match the FP64 oracle to 1e-4; the
+    difference is the binary32 storage, which moves a few ill-conditioned
+    options by more than 2e-3)."""
     import numpy as np
     import torch
     import paper_1205_0106_amd as amq
@@ -377,6 +384,7 @@ def batch_vs_single(n, steps, warmup):
             "single_option_fp64": {"value": total / dt64, "ms_for_all": 1e3 * dt64},
             "speedup": dt64 / dt32,
             "max_abs_price_diff": float(diff.max()), "median_abs_price_diff": float(np.median(diff)),
+            "n_price_diff_over_2e-3": int((diff > 2e-3).sum()),
             "median_naive_std_err": float(np.median(p64[:, 1])),
             "unit": "path-steps/s"}
 
@@ -480,16 +488,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        # arithmetic of the path: FP32 bulk computes the inverse normal in
-        # binary32 and everything after it in binary64 (path values and
-        # cashflows stored in binary32); FP64 is binary64 throughout
+        # arithmetic of the path: FP32 bulk computes in binary64 and stores
+        # path values and cashflows in binary32 (each rounded once); FP64 is
+        # binary64 throughout
         "dtype": "f32+f64" if dtype == "fp32" else "f64",
         "data": "synthetic (on-device Sobol paths)",
         "config": {"workload": w.name, "n_paths": w.n_paths, "n_dates": w.n_dates,
                    "basis": f"{w.basis[0]} degree {w.basis[1]}",
                    "storage": "f32" if dtype == "fp32" else "f64",
-                   "precision": ("FP32 bulk: binary32 path values and cashflows, binary32 inverse normal, "
-                                 "binary64 bridge, exponent, regression, solve and sums")
+                   "precision": ("FP32 bulk: binary32 storage of path values and cashflows (each rounded "
+                                 "once from binary64); binary64 inverse normal, bridge, exponent, "
+                                 "regression, solve and sums")
                    if dtype == "fp32" else "FP64 throughout",
                    "S0": w.S0, "K": w.K, "r": w.r, "sigma": w.sigma, "T": w.T},
         "roofline": roofline,
@@ -499,7 +508,7 @@ def main():
         "price": m["price"],
         "std_err": m["std_err"],
     }
-    for k in ("oracle_price", "abs_err_vs_oracle"):
+    for k in ("oracle_price", "abs_err_vs_oracle", "abs_err_vs_binary64_oracle"):
         if k in m:
             out[k] = m[k]
     if dtype == "fp32" and "fp64" in w.dtypes and not args.no_fp64_side:
@@ -518,7 +527,8 @@ def main():
                 m2 = single_run(amq, pricer, w2, d2, args.steps, args.warmup)
                 extra[d2] = {"value": m2["value"], "ms_per_step": 1e3 * m2["seconds"] / args.steps,
                              "phase_ms": {"generate": round(m2["gen_ms"], 4), "sweep": round(m2["sweep_ms"], 4)},
-                             "price": m2["price"], "abs_err_vs_oracle": m2.get("abs_err_vs_oracle")}
+                             "price": m2["price"], "abs_err_vs_oracle": m2.get("abs_err_vs_oracle"),
+                             "abs_err_vs_binary64_oracle": m2.get("abs_err_vs_binary64_oracle")}
             out["config2"] = extra
             pricer.ws = None
             torch.cuda.empty_cache()

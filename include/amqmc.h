@@ -58,12 +58,17 @@ enum { AM_MAX_DEGREE = 6 };
 
 /* Arithmetic of the bulk path data.
  *   AM_FP64:      everything binary64.
- *   AM_FP32_BULK: path values and per-path cashflows stored in binary32
- *                 (half the HBM traffic and footprint); the inverse normal
- *                 in binary32; the bridge, the exponent and every step of the
- *                 backward induction in binary64 on those stored values (the
- *                 least-squares fit and the exercise test react to relative
- *                 perturbations near 1e-8 for some options). */
+ *   AM_FP32_BULK: path values and per-path cashflows (discounted to t0)
+ *                 stored in binary32, each rounded once from its binary64
+ *                 value (half the HBM traffic and footprint); the inverse
+ *                 normal, the bridge, the exponent and every step of the
+ *                 backward induction in binary64 (the least-squares fit and
+ *                 the exercise test react to relative perturbations near
+ *                 1e-8, and to single-ulp changes of the stored values, for
+ *                 some options).  The result is the method on binary32
+ *                 storage; for a few ill-conditioned options that storage
+ *                 alone moves the price by more than 2e-3 from the binary64
+ *                 result. */
 enum { AM_FP64 = 0, AM_FP32_BULK = 1 };
 
 /* Storage rule for small requests.  With fewer than AM_FP32_MIN_PATHS paths a

@@ -128,6 +128,11 @@ def _configure(L):
                                             ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             P(ctypes.c_uint32), P(_Result), P(ctypes.c_double),
                                             P(ctypes.c_int32), P(ctypes.c_double)]
+    L.or_price_american_stored.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           P(ctypes.c_uint32), ctypes.c_int, P(_Result),
+                                           P(ctypes.c_double), P(ctypes.c_int32),
+                                           P(ctypes.c_double)]
     L.or_paths_range_shifted.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64,
                                          ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint32),
                                          P(ctypes.c_double)]
@@ -135,6 +140,10 @@ def _configure(L):
                                  ctypes.c_int, P(ctypes.c_double)]
     L.or_basis_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 P(ctypes.c_double)]
+    L.or_lsm_on_paths_stored.argtypes = [P(ctypes.c_double), ctypes.c_int64, ctypes.c_int,
+                                         P(_Params), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         P(_Result), P(ctypes.c_double), P(ctypes.c_int32),
+                                         P(ctypes.c_int32), P(ctypes.c_double)]
     L.or_lsm_on_paths.argtypes = [P(ctypes.c_double), ctypes.c_int64, ctypes.c_int,
                                   P(_Params), ctypes.c_int, ctypes.c_int, P(_Result),
                                   P(ctypes.c_double), P(ctypes.c_int32),
@@ -259,8 +268,10 @@ def basis_eval(kind: int, degree: int, x: float) -> np.ndarray:
 
 
 def lsm_on_paths(S: np.ndarray, S0, K, r, sigma, T, *, is_call=False, allow_exercise=True,
-                 kind=MONOMIAL, degree=2, detail=False):
-    """Least-squares backward induction on a given path matrix S[M][N]."""
+                 kind=MONOMIAL, degree=2, detail=False, store32=False):
+    """Least-squares backward induction on a given path matrix S[M][N].
+    store32: binary32 storage (path values read rounded to binary32, cashflows
+    held discounted to t0 and rounded to binary32), binary64 arithmetic."""
     S = np.ascontiguousarray(S, dtype=np.float64)
     M, N = S.shape
     p = _params(S0, K, r, sigma, T, is_call, allow_exercise)
@@ -269,10 +280,10 @@ def lsm_on_paths(S: np.ndarray, S0, K, r, sigma, T, *, is_call=False, allow_exer
     nitm = np.zeros(M + 1, dtype=np.int32)
     tau = np.zeros(N, dtype=np.int32)
     pv = np.zeros(N, dtype=np.float64)
-    rc = lib().or_lsm_on_paths(_ptr(S, ctypes.c_double), N, M, ctypes.byref(p), kind, degree,
-                               ctypes.byref(res), _ptr(beta, ctypes.c_double),
-                               _ptr(nitm, ctypes.c_int32), _ptr(tau, ctypes.c_int32),
-                               _ptr(pv, ctypes.c_double))
+    rc = lib().or_lsm_on_paths_stored(_ptr(S, ctypes.c_double), N, M, ctypes.byref(p), kind, degree,
+                                      int(bool(store32)), ctypes.byref(res), _ptr(beta, ctypes.c_double),
+                                      _ptr(nitm, ctypes.c_int32), _ptr(tau, ctypes.c_int32),
+                                      _ptr(pv, ctypes.c_double))
     if rc != 0:
         raise RuntimeError(f"or_lsm_on_paths failed ({rc})")
     out = OracleResult(res.price, res.std_err, res.mean_pv, bool(res.t0_exercise), res.n_skipped)
@@ -282,18 +293,20 @@ def lsm_on_paths(S: np.ndarray, S0, K, r, sigma, T, *, is_call=False, allow_exer
 
 
 def price_american(S0, K, r, sigma, T, N: int, M: int, *, is_call=False, allow_exercise=True,
-                   kind=MONOMIAL, degree=2, detail=False):
-    """The full oracle on Sobol points: returns OracleResult (and details)."""
+                   kind=MONOMIAL, degree=2, detail=False, store32=False):
+    """The full oracle on Sobol points: returns OracleResult (and details).
+    store32: binary32 storage of the path values and cashflows (the FP32-bulk
+    reading; see lsm_on_paths), binary64 arithmetic."""
     p = _params(S0, K, r, sigma, T, is_call, allow_exercise)
     V = directions(M)
     res = _Result()
     beta = np.zeros((M + 1, BETA_STRIDE), dtype=np.float64)
     nitm = np.zeros(M + 1, dtype=np.int32)
     pv = np.zeros(N, dtype=np.float64) if detail else None
-    rc = lib().or_price_american(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, kind, degree,
-                                 ctypes.byref(res), _ptr(beta, ctypes.c_double),
-                                 _ptr(nitm, ctypes.c_int32),
-                                 _ptr(pv, ctypes.c_double) if pv is not None else None)
+    rc = lib().or_price_american_stored(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, kind,
+                                        degree, None, int(bool(store32)), ctypes.byref(res),
+                                        _ptr(beta, ctypes.c_double), _ptr(nitm, ctypes.c_int32),
+                                        _ptr(pv, ctypes.c_double) if pv is not None else None)
     if rc != 0:
         raise RuntimeError(f"or_price_american failed ({rc})")
     out = OracleResult(res.price, res.std_err, res.mean_pv, bool(res.t0_exercise), res.n_skipped)
@@ -307,7 +320,7 @@ def inv_normal_mid_u32(x: int) -> float:
 
 
 def price_american_rqmc(S0, K, r, sigma, T, N: int, M: int, shifts: np.ndarray, *, is_call=False,
-                        allow_exercise=True, kind=MONOMIAL, degree=2):
+                        allow_exercise=True, kind=MONOMIAL, degree=2, store32=False):
     """Randomised QMC: one price per digital-shift replicate (shifts: uint32
     [R][M]).  Returns (mean, sd/sqrt(R), per-replicate prices)."""
     p = _params(S0, K, r, sigma, T, is_call, allow_exercise)
@@ -317,11 +330,11 @@ def price_american_rqmc(S0, K, r, sigma, T, N: int, M: int, shifts: np.ndarray, 
     for row in shifts:
         res = _Result()
         row = np.ascontiguousarray(row)
-        rc = lib().or_price_american_shifted(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, kind,
-                                             degree, _ptr(row, ctypes.c_uint32), ctypes.byref(res),
-                                             None, None, None)
+        rc = lib().or_price_american_stored(ctypes.byref(p), _ptr(V, ctypes.c_uint32), N, M, kind,
+                                            degree, _ptr(row, ctypes.c_uint32), int(bool(store32)),
+                                            ctypes.byref(res), None, None, None)
         if rc != 0:
-            raise RuntimeError("or_price_american_shifted failed")
+            raise RuntimeError("or_price_american_stored failed")
         prices.append(res.price)
     prices = np.array(prices)
     R = len(prices)

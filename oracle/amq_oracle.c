@@ -318,22 +318,47 @@ static void givens_row(int p, double R[OR_MAXP][OR_MAXP], double *qy,
 /* Backward induction (Section V; least-squares continuation of [12]).       */
 /* CF/tau hold each path's cashflow and its stopping date; the regression    */
 /* target at date k is the realised cashflow discounted back to t_k.         */
+/*                                                                          */
+/* store32 != 0: binary32 storage.  Every path value is read rounded to the  */
+/* nearest binary32, and every cashflow is held as its value discounted to   */
+/* t0 rounded to the nearest binary32 (PV32); the regression target at t_k   */
+/* is then PV32 carried forward to t_k.  All arithmetic stays binary64.      */
 /* ------------------------------------------------------------------------ */
+static double rd32(double v) { return (double)(float)v; }   /* round to nearest */
+
 int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
                     int kind, int degree, or_result *res,
                     double *beta_out, int32_t *nitm_out, int32_t *tau_out,
                     double *pv_out)
+{
+    return or_lsm_on_paths_stored(S, N, M, p, kind, degree, 0, res, beta_out, nitm_out,
+                                  tau_out, pv_out);
+}
+
+int or_lsm_on_paths_stored(const double *S, int64_t N, int M, const or_params *p,
+                           int kind, int degree, int store32, or_result *res,
+                           double *beta_out, int32_t *nitm_out, int32_t *tau_out,
+                           double *pv_out)
 {
     int np = degree + 1;
     if (N < 1 || M < 1 || np < 1 || np > OR_MAXP) return -1;
     double *CF = (double *)malloc(sizeof(double) * (size_t)N);
     int32_t *tau = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     double *t = (double *)malloc(sizeof(double) * (size_t)(M + 1));
-    if (!CF || !tau || !t) { free(CF); free(tau); free(t); return -2; }
+    double *PV32 = store32 ? (double *)malloc(sizeof(double) * (size_t)N) : NULL;
+    if (!CF || !tau || !t || (store32 && !PV32)) {
+        free(CF); free(tau); free(t); free(PV32);
+        return -2;
+    }
     for (int k = 0; k <= M; ++k) t[k] = (double)k * p->T / (double)M;
+#define SV(x) (store32 ? rd32(x) : (x))
 
     const double *last = S + (int64_t)(M - 1) * N;
-    for (int64_t i = 0; i < N; ++i) { CF[i] = payoff(p, last[i]); tau[i] = M; }
+    for (int64_t i = 0; i < N; ++i) {
+        CF[i] = payoff(p, SV(last[i]));
+        tau[i] = M;
+        if (store32) PV32[i] = rd32(CF[i] * exp(-p->r * t[M]));
+    }
     if (beta_out) for (int64_t q = 0; q < (int64_t)(M + 1) * OR_BETA_STRIDE; ++q) beta_out[q] = 0.0;
     if (nitm_out) for (int k = 0; k <= M; ++k) nitm_out[k] = 0;
 
@@ -342,7 +367,7 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
         for (int k = M - 1; k >= 1; --k) {
             const double *row = S + (int64_t)(k - 1) * N;
             int64_t nitm = 0;
-            for (int64_t i = 0; i < N; ++i) if (payoff(p, row[i]) > 0.0) ++nitm;
+            for (int64_t i = 0; i < N; ++i) if (payoff(p, SV(row[i])) > 0.0) ++nitm;
             if (nitm_out) nitm_out[k] = (int32_t)nitm;
             if (nitm < np) { ++skipped; continue; }
 
@@ -350,10 +375,12 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
             double qy[OR_MAXP], psi[OR_MAXP], beta[OR_MAXP];
             memset(R, 0, sizeof(R)); memset(qy, 0, sizeof(qy));
             for (int64_t i = 0; i < N; ++i) {
-                double h = payoff(p, row[i]);
+                const double s = SV(row[i]);
+                double h = payoff(p, s);
                 if (!(h > 0.0)) continue;
-                or_basis_eval(kind, degree, row[i] / p->K, psi);
-                double y = CF[i] * exp(-p->r * (t[tau[i]] - t[k]));
+                or_basis_eval(kind, degree, s / p->K, psi);
+                double y = store32 ? PV32[i] * exp(p->r * t[k])
+                                   : CF[i] * exp(-p->r * (t[tau[i]] - t[k]));
                 givens_row(np, R, qy, psi, y);
             }
             double dmax = 0.0, dmin = INFINITY;
@@ -373,20 +400,26 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
                 beta_out[(int64_t)k * OR_BETA_STRIDE + OR_MAXP] = 1.0;   /* valid flag */
             }
             for (int64_t i = 0; i < N; ++i) {
-                double h = payoff(p, row[i]);
+                const double s = SV(row[i]);
+                double h = payoff(p, s);
                 if (!(h > 0.0)) continue;
-                or_basis_eval(kind, degree, row[i] / p->K, psi);
+                or_basis_eval(kind, degree, s / p->K, psi);
                 double cont = 0.0;
                 for (int j = 0; j < np; ++j) cont += psi[j] * beta[j];
-                if (h > cont) { CF[i] = h; tau[i] = k; }
+                if (h > cont) {
+                    CF[i] = h;
+                    tau[i] = k;
+                    if (store32) PV32[i] = rd32(h * exp(-p->r * t[k]));
+                }
             }
         }
     }
 
     /* eqs. (6)-(8): per-path cashflow discounted to t0, then the mean. */
     ksum sum = {0.0, 0.0};
+#undef SV
     for (int64_t i = 0; i < N; ++i) {
-        double pv = CF[i] * exp(-p->r * t[tau[i]]);
+        double pv = store32 ? PV32[i] : CF[i] * exp(-p->r * t[tau[i]]);
         if (pv_out) pv_out[i] = pv;
         if (tau_out) tau_out[i] = tau[i];
         CF[i] = pv;
@@ -407,7 +440,7 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
         double h0 = payoff(p, p->S0);
         if (h0 > mean) { res->price = h0; res->std_err = 0.0; res->t0_exercise = 1; }
     }
-    free(CF); free(tau); free(t);
+    free(CF); free(tau); free(t); free(PV32);
     return 0;
 }
 
@@ -423,12 +456,21 @@ int or_price_american_shifted(const or_params *p, const uint32_t *V, int64_t N, 
                               int kind, int degree, const uint32_t *shift, or_result *res,
                               double *beta_out, int32_t *nitm_out, double *pv_out)
 {
+    return or_price_american_stored(p, V, N, M, kind, degree, shift, 0, res, beta_out,
+                                    nitm_out, pv_out);
+}
+
+int or_price_american_stored(const or_params *p, const uint32_t *V, int64_t N, int M,
+                             int kind, int degree, const uint32_t *shift, int store32,
+                             or_result *res, double *beta_out, int32_t *nitm_out,
+                             double *pv_out)
+{
     if (N < 1 || M < 1) return -1;
     double *S = (double *)malloc(sizeof(double) * (size_t)N * (size_t)M);
     if (!S) return -2;
     int rc = or_paths_range_shifted(p, V, 0, N, M, shift, S);
-    if (rc == 0) rc = or_lsm_on_paths(S, N, M, p, kind, degree, res, beta_out,
-                                      nitm_out, NULL, pv_out);
+    if (rc == 0) rc = or_lsm_on_paths_stored(S, N, M, p, kind, degree, store32, res, beta_out,
+                                             nitm_out, NULL, pv_out);
     free(S);
     return rc;
 }

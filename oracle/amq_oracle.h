@@ -79,6 +79,16 @@ int or_lsm_on_paths(const double *S, int64_t N, int M, const or_params *p,
                     double *beta_out, int32_t *nitm_out, int32_t *tau_out,
                     double *pv_out);
 
+/* Same, with binary32 storage when store32 != 0: path values read rounded to
+ * binary32, cashflows held discounted to t0 and rounded to binary32; all
+ * arithmetic binary64.  The paper fixes no storage precision; this is the
+ * method on binary32 storage, the definition the GPU's FP32-bulk mode is
+ * checked against. */
+int or_lsm_on_paths_stored(const double *S, int64_t N, int M, const or_params *p,
+                           int kind, int degree, int store32, or_result *res,
+                           double *beta_out, int32_t *nitm_out, int32_t *tau_out,
+                           double *pv_out);
+
 /* Full oracle: Sobol -> inverse normal -> bridge -> GBM -> LSM -> mean. */
 int or_price_american(const or_params *p, const uint32_t *V, int64_t N, int M,
                       int kind, int degree, or_result *res,
@@ -88,6 +98,13 @@ int or_price_american(const or_params *p, const uint32_t *V, int64_t N, int M,
 int or_price_american_shifted(const or_params *p, const uint32_t *V, int64_t N, int M,
                               int kind, int degree, const uint32_t *shift, or_result *res,
                               double *beta_out, int32_t *nitm_out, double *pv_out);
+
+/* Same again, optionally on binary32 storage (store32 != 0, as in
+ * or_lsm_on_paths_stored). */
+int or_price_american_stored(const or_params *p, const uint32_t *V, int64_t N, int M,
+                             int kind, int degree, const uint32_t *shift, int store32,
+                             or_result *res, double *beta_out, int32_t *nitm_out,
+                             double *pv_out);
 
 /* The paper's own estimator: Black–Scholes over the last interval, then a
  * per-path backward maximum (eqs. (10)-(11)). */

@@ -885,7 +885,7 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
     pa.ticket = (uint32_t *)(ws + L.off_result + 64) + 4;
     pa.result = (double *)(ws + L.off_result);
     pa.N = n_paths; pa.ld = L.ld; pa.m = n_points; pa.is_call = params->is_call;
-    pa.K = params->K; pa.r = params->r; pa.sigma = params->sigma; pa.dt = dt;
+    pa.K = params->K; pa.r = params->r; pa.sigma = params->sigma; pa.dt = dt; pa.S0 = params->S0;
     HIP_TRY(amq::launch_paper(pa, fp64, stream));
     if (!h_out) return AM_OK;
     return fetch_result(ws, L, stream, h_out);

@@ -114,7 +114,7 @@ struct PaperArgs {
     double *result;           // [8]
     int64_t N, ld;
     int32_t m, is_call;
-    double K, r, sigma, dt;
+    double K, r, sigma, dt, S0;
 };
 
 // One option of a batch, as the kernels see it (all pointers into the

@@ -44,60 +44,37 @@ namespace amq {
 #define AMQ_C8 0.0000003960315187
 
 // The two branches separately: which branch a point takes, the central
-// rational function and the tail polynomial.  inv_normal_f32/_f64 combine
-// them; the binary64 path generator evaluates the tails packed.
+// rational function and the tail polynomial (its two logarithms by log_f64,
+// about 1 ulp).  inv_normal_f64 combines them; the path generator evaluates
+// the tails packed.
 template <typename T> struct MoroParts;
 
-template <> struct MoroParts<float> {
-    static __device__ __forceinline__ bool tail(uint32_t x)
-    {
-        const float y = (float)(int32_t)(x - 0x80000000u) * 0x1p-32f;
-        return !(fabsf(y) < 0.42f);
-    }
-    static __device__ __forceinline__ float central(uint32_t x)
-    {
-        const float y = (float)(int32_t)(x - 0x80000000u) * 0x1p-32f;
-        const float r = y * y;
-        const float num = y * fmaf(fmaf(fmaf((float)AMQ_A3, r, (float)AMQ_A2), r, (float)AMQ_A1), r,
-                                   (float)AMQ_A0);
-        const float den = fmaf(fmaf(fmaf(fmaf((float)AMQ_B3, r, (float)AMQ_B2), r, (float)AMQ_B1), r,
-                                    (float)AMQ_B0), r, 1.0f);
-        return num * __builtin_amdgcn_rcpf(den);
-    }
-    static __device__ __forceinline__ float tail_value(uint32_t x)
-    {
-        const int32_t d = (int32_t)(x - 0x80000000u);
-        const uint32_t tq = d < 0 ? x : 0u - x;
-        const float q = (float)tq * 0x1p-32f;
-        const float ln2 = 0.69314718055994531f;
-        const float t = __builtin_amdgcn_logf(-__builtin_amdgcn_logf(q) * ln2) * ln2;
-        float v = (float)AMQ_C8;
-        v = fmaf(v, t, (float)AMQ_C7);
-        v = fmaf(v, t, (float)AMQ_C6);
-        v = fmaf(v, t, (float)AMQ_C5);
-        v = fmaf(v, t, (float)AMQ_C4);
-        v = fmaf(v, t, (float)AMQ_C3);
-        v = fmaf(v, t, (float)AMQ_C2);
-        v = fmaf(v, t, (float)AMQ_C1);
-        v = fmaf(v, t, (float)AMQ_C0);
-        return d < 0 ? -v : v;
-    }
-};
-
 template <> struct MoroParts<double> {
+    // d = x - 2^31 exactly (the sign bit flipped, read as a signed integer);
+    // y = u - 1/2 = d 2^-32.  The branch test and the central rational are
+    // taken on d with every constant scaled by a power of two, which leaves
+    // each rounded intermediate scaled by the same power: the values are
+    // bitwise those of the same steps on y (no under- or overflow here).
+    static __device__ __forceinline__ double centered(uint32_t x)
+    {
+        return (double)(int32_t)(x ^ 0x80000000u);
+    }
     static __device__ __forceinline__ bool tail(uint32_t x)
     {
-        const double y = ((double)x - 2147483648.0) * 0x1p-32;
-        return !(fabs(y) < 0.42);
+        return !(fabs(centered(x)) < 0.42 * 0x1p32);   // |y| >= 0.42
     }
     static __device__ __forceinline__ double central(uint32_t x)
     {
-        const double y = ((double)x - 2147483648.0) * 0x1p-32;
-        const double r = y * y;
-        // the fused steps the compiler forms from the plain expression, in
-        // the three-address form
-        const double num = y * fma3(fma3(fma3(AMQ_A3, r, AMQ_A2), r, AMQ_A1), r, AMQ_A0);
-        const double den = fma(fma3(fma3(fma3(AMQ_B3, r, AMQ_B2), r, AMQ_B1), r, AMQ_B0), r, 1.0);
+        // y P(r) / Q(r), r = y^2 = D 2^-64: Horner in D with the k-th
+        // coefficient of P scaled by 2^(-64k - 32) (the y factor's 2^-32
+        // folded in) and of Q (beyond the constant 1) by 2^(-64(k + 1))
+        const double d = centered(x);
+        const double D = d * d;
+        const double num = d * fma3(fma3(fma3(AMQ_A3 * 0x1p-224, D, AMQ_A2 * 0x1p-160), D, AMQ_A1 * 0x1p-96),
+                                    D, AMQ_A0 * 0x1p-32);
+        const double den = fma(fma3(fma3(fma3(AMQ_B3 * 0x1p-256, D, AMQ_B2 * 0x1p-192), D, AMQ_B1 * 0x1p-128),
+                                    D, AMQ_B0 * 0x1p-64),
+                               D, 1.0);
         return num * rcp_f64(den);   // (a tail point's value is discarded)
     }
     static __device__ __forceinline__ double tail_value(uint32_t x)
@@ -105,7 +82,7 @@ template <> struct MoroParts<double> {
         const double s = 0x1p-32;
         const double y = ((double)x - 2147483648.0) * s;
         const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
-        const double t = log(-log(q));
+        const double t = log_f64(-log_f64(q));
         double v = AMQ_C8;
         v = v * t + AMQ_C7;
         v = v * t + AMQ_C6;
@@ -119,14 +96,6 @@ template <> struct MoroParts<double> {
     }
 };
 
-// binary32: both branches are evaluated (every 64-point Sobol block has tail
-// lanes), hardware log2/rcp; y and q come exactly from the 32-bit integer.
-__device__ __forceinline__ float inv_normal_f32(uint32_t x)
-{
-    const float zc = MoroParts<float>::central(x), zt = MoroParts<float>::tail_value(x);
-    return MoroParts<float>::tail(x) ? zt : zc;
-}
-
 // binary64: u, u - 1/2 and 1 - u are exact for u = x 2^-32.
 __device__ __forceinline__ double inv_normal_f64(uint32_t x)
 {
@@ -135,34 +104,6 @@ __device__ __forceinline__ double inv_normal_f64(uint32_t x)
 
 // Shifted (randomised) points sit at cell midpoints u = (x + 1/2) 2^-32, so a
 // shifted integer 0 still maps to a finite normal.
-__device__ __forceinline__ float inv_normal_mid_f32(uint32_t x)
-{
-    const float s = 0x1p-32f;
-    const int32_t d = (int32_t)(x - 0x80000000u);
-    const float y = ((float)d + 0.5f) * s;
-    const float r = y * y;
-    const float num = y * fmaf(fmaf(fmaf((float)AMQ_A3, r, (float)AMQ_A2), r, (float)AMQ_A1), r,
-                               (float)AMQ_A0);
-    const float den = fmaf(fmaf(fmaf(fmaf((float)AMQ_B3, r, (float)AMQ_B2), r, (float)AMQ_B1), r,
-                                (float)AMQ_B0), r, 1.0f);
-    const float zc = num * __builtin_amdgcn_rcpf(den);
-    const uint32_t tq = d < 0 ? x : 0u - x;
-    const float q = fmaf((float)tq, s, d < 0 ? 0x1p-33f : -0x1p-33f);
-    const float ln2 = 0.69314718055994531f;
-    const float t = __builtin_amdgcn_logf(-__builtin_amdgcn_logf(q) * ln2) * ln2;
-    float v = (float)AMQ_C8;
-    v = fmaf(v, t, (float)AMQ_C7);
-    v = fmaf(v, t, (float)AMQ_C6);
-    v = fmaf(v, t, (float)AMQ_C5);
-    v = fmaf(v, t, (float)AMQ_C4);
-    v = fmaf(v, t, (float)AMQ_C3);
-    v = fmaf(v, t, (float)AMQ_C2);
-    v = fmaf(v, t, (float)AMQ_C1);
-    v = fmaf(v, t, (float)AMQ_C0);
-    const float zt = d < 0 ? -v : v;
-    return fabsf(y) < 0.42f ? zc : zt;
-}
-
 __device__ __forceinline__ double inv_normal_mid_f64(uint32_t x)
 {
     const double s = 0x1p-32;
@@ -174,7 +115,7 @@ __device__ __forceinline__ double inv_normal_mid_f64(uint32_t x)
         return num / den;
     }
     const double q = y < 0.0 ? ((double)x + 0.5) * s : (4294967296.0 - (double)x - 0.5) * s;
-    const double t = log(-log(q));
+    const double t = log_f64(-log_f64(q));
     double v = AMQ_C8;
     v = v * t + AMQ_C7;
     v = v * t + AMQ_C6;
@@ -187,11 +128,10 @@ __device__ __forceinline__ double inv_normal_mid_f64(uint32_t x)
     return y < 0.0 ? -v : v;
 }
 
-template <typename T, bool MID> __device__ __forceinline__ T inv_normal(uint32_t x);
-template <> __device__ __forceinline__ float inv_normal<float, false>(uint32_t x) { return inv_normal_f32(x); }
-template <> __device__ __forceinline__ double inv_normal<double, false>(uint32_t x) { return inv_normal_f64(x); }
-template <> __device__ __forceinline__ float inv_normal<float, true>(uint32_t x) { return inv_normal_mid_f32(x); }
-template <> __device__ __forceinline__ double inv_normal<double, true>(uint32_t x) { return inv_normal_mid_f64(x); }
+template <bool MID> __device__ __forceinline__ double inv_normal(uint32_t x)
+{
+    return MID ? inv_normal_mid_f64(x) : inv_normal_f64(x);
+}
 
 // A bridge node as the batch generator keeps it in LDS.
 struct LdsNode {
@@ -206,11 +146,12 @@ constexpr int kTailChunk = 5;
 
 __host__ __device__ size_t generate_lds_bytes(int M, int fp64)
 {
-    // lane tables [M][16], per-wave block words [kWaves][M][2]; binary64:
-    // per-wave tail staging, points [kTailChunk * 64] u32 and normals
-    // [kTailChunk * 64] f64
+    // lane tables [M][16], per-wave block words [kWaves][M][2], per-wave tail
+    // staging: points [kTailChunk * 64] u32 and normals [kTailChunk * 64] f64
+    // (both storage types: the normals are binary64)
+    (void)fp64;
     return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t) +
-           (fp64 ? (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 : 0);
+           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8;
 }
 
 // ---------------------------------------------------------------------------
@@ -244,7 +185,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
     // this wave's tail staging (see kTailChunk)
     uint32_t *tx = lds + (size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)wave * kTailChunk * 64;
-    T *tz = reinterpret_cast<T *>(reinterpret_cast<char *>(lds) +
+    double *tz = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) +
                                   (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * kTailChunk * 64) *
                                        sizeof(uint32_t) + 7) / 8 * 8) +
             (size_t)wave * kTailChunk * 64;
@@ -317,12 +258,13 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     const int offL = gl & 7, offH = 8 + (gl >> 3);
     const int xsel = lane == 63 ? 1 : 0;
 
-    // The bridge and the exponent run in binary64 for both storage types
-    // (binary32 storage: an exponential good to 3e-10, rounded once to
-    // binary32; the exercise decisions
-    // downstream are sensitive to path-value errors well below a binary32 ulp,
-    // so nothing but the final rounding is left in binary32).  Only the
-    // inverse normal is evaluated in the storage precision.  The bridge runs
+    // The inverse normal, the bridge and the exponent run in binary64 for
+    // both storage types, so binary32 storage holds each path value rounded
+    // once from its binary64 value (the correctly rounded value except where
+    // that lies within a few binary64 ulps of a rounding boundary).  The
+    // exercise decisions downstream react to path-value errors of one
+    // binary32 ulp on some options (a binary32 inverse normal moved prices by
+    // up to 7e-2).  The bridge runs
     // on the log-price X(t_m) = log S0 + mu m + vol W(m) (the schedule's
     // weights sum to 1, so interpolation carries the constant and the drift),
     // and S = exp(X): no per-date drift, volatility or S0 products.
@@ -350,11 +292,9 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             for (int m = 0; m < M; ++m) ((T *)a.S)[(size_t)m * a.ld + i] = Kp;
             continue;
         }
-        if constexpr (WHAT == 0 && !MID && sizeof(T) == 8) {
-            // binary64 paths: the inverse normal's two branches evaluated
-            // apart (the tail's two library logarithms dominate; in binary32,
-            // with hardware logarithms, evaluating both branches in every lane
-            // is cheaper than the packing).  Every
+        if constexpr (WHAT == 0 && !MID) {
+            // the inverse normal's two branches evaluated apart (the tail's
+            // two logarithms dominate).  Every
             // lane evaluates the (cheap) central branch; the points in the tails
             // of kTailChunk nodes are packed into this wave's LDS staging
             // (ballot and lane rank), their tail values evaluated together,
@@ -371,7 +311,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                         const int j = __builtin_amdgcn_readfirstlane(sched[s0 + q].dim);
                         const uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
                         xs[q] = x;
-                        tl[q] = MoroParts<T>::tail(x);
+                        tl[q] = MoroParts<double>::tail(x);
                         const uint64_t m = __builtin_amdgcn_ballot_w64(tl[q]);
                         slot[q] = ntail + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -384,7 +324,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 for (uint32_t t0 = 0; t0 < ntail; t0 += 64) {
                     const uint32_t t = t0 + (uint32_t)lane;
-                    if (t < ntail) tz[t] = MoroParts<T>::tail_value(tx[t]);
+                    if (t < ntail) tz[t] = MoroParts<double>::tail_value(tx[t]);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -399,11 +339,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                                   n_dst = __builtin_amdgcn_readfirstlane(nd.dst);
                         const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr),
                                      n_sd = uniform_f64(nd.sd);
-                        const T zc = MoroParts<T>::central(xs[q]);
-                        const T z = tl[q] ? tz[slot[q]] : zc;
-                        const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * (double)z);
+                        const double zc = MoroParts<double>::central(xs[q]);
+                        const double z = tl[q] ? tz[slot[q]] : zc;
+                        const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * z);
                         X[n_dst] = xv;
-                        const T Sv = (T)(sizeof(T) == 4 ? exp_poly_f32(xv) : exp_poly<true>(xv));
+                        const T Sv = (T)exp_poly<true>(xv);
                         ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
                     }
                 }
@@ -431,14 +371,14 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 if (valid) ((uint32_t *)a.S)[(size_t)j * a.ld + i] = x;
                 continue;
             }
-            const T z = inv_normal<T, MID>(x);
+            const double z = inv_normal<MID>(x);
             if (WHAT == 2) {
-                if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = (double)z;
+                if (valid) ((double *)a.S)[(size_t)j * a.ld + i] = z;
                 continue;
             }
-            const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * (double)z);
+            const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * z);
             X[n_dst] = xv;
-            const T Sv = (T)(sizeof(T) == 4 ? exp_poly_f32(xv) : exp_poly<true>(xv));
+            const T Sv = (T)exp_poly<true>(xv);
             ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {
@@ -458,9 +398,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     }
 }
 
-// four waves per SIMD for binary32 storage (at most 128 VGPRs), three for
-// binary64 (its packed tail evaluation with the library logarithm needs the
-// room):
+// three waves per SIMD (the packed tail evaluation needs the registers):
 // latency hiding for the per-lane dependency chain of each path through the
 // dates
 template <typename T, int WHAT, bool MID>
@@ -496,8 +434,8 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
     } else if (a.what == 1) {
         hipLaunchKernelGGL((gen_kernel<float, 1, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
     } else {
-        if (fp64) hipLaunchKernelGGL((gen_kernel<double, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
-        else      hipLaunchKernelGGL((gen_kernel<float, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        // the normals are binary64 for both storage types
+        hipLaunchKernelGGL((gen_kernel<double, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
     }
     return hipGetLastError();
 }
@@ -717,6 +655,10 @@ __global__ void __launch_bounds__(kWG) paper_kernel(PaperArgs a, const T *__rest
     const T K = (T)a.K, r = (T)a.r, sig = (T)a.sigma, dt = (T)a.dt;
     const T disc = (T)exp(-a.r * a.dt);
     const bool call = a.is_call != 0;
+    // sums about c = max(h(S0), 0): the variance below cancels only to the
+    // order of (mean - c)^2 / variance
+    const double h0 = call ? a.S0 - a.K : a.K - a.S0;
+    const double csh = h0 > 0.0 ? h0 : 0.0;
     double acc[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < a.N; i += (int64_t)gridDim.x * kWG) {
         T v = T(0);
@@ -727,7 +669,7 @@ __global__ void __launch_bounds__(kWG) paper_kernel(PaperArgs a, const T *__rest
             const T cont = (k == a.m) ? bs_value<T>(s, K, r, sig, dt, call) : disc * v;
             v = h > cont ? h : cont;
         }
-        const double c = (double)disc * (double)v;
+        const double c = (double)disc * (double)v - csh;
         acc[0] += c;
         acc[1] += c * c;
     }
@@ -744,8 +686,8 @@ __global__ void __launch_bounds__(kWG) paper_kernel(PaperArgs a, const T *__rest
     reduce_partials<2>(a.part, gridDim.x, s_tot, s_red8);
     if (threadIdx.x == 0) {
         const double n = (double)a.N;
-        const double mean = s_tot[0] / n;
-        double var = a.N > 1 ? (s_tot[1] - s_tot[0] * mean) / (n - 1.0) : 0.0;
+        const double mean = csh + s_tot[0] / n;
+        double var = a.N > 1 ? (s_tot[1] - s_tot[0] * (s_tot[0] / n)) / (n - 1.0) : 0.0;
         if (var < 0.0) var = 0.0;
         a.result[0] = mean;
         a.result[1] = sqrt(var / n);

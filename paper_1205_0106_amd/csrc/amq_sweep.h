@@ -1107,7 +1107,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const T *__restri
 }
 
 // Epilogue (eqs. (6)-(8)): FP64 sums of the discounted cashflows and their
-// squares through one more device-wide sum; group 0 writes the result.
+// squares through one more device-wide sum; group 0 writes the result.  The
+// sums are taken about the shift c = max(h(S0), 0), a value of the order of
+// the mean for options in the money and zero otherwise, so the variance
+// (sum of squares minus the squared sum over n) cancels only to the order of
+// (mean - c)^2 / variance instead of mean^2 / variance.
+__device__ __forceinline__ double moment_shift(const SweepArgs &a)
+{
+    const double h0 = a.is_call ? a.S0 - a.K : a.K - a.S0;
+    return h0 > 0.0 ? h0 : 0.0;
+}
+
 template <typename T, int PPT, int D, int WG>
 __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, uint32_t e0,
                                             const T (&pv)[PPT], uint32_t epoch, double (*s_red)[32],
@@ -1117,6 +1127,7 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
     constexpr uint32_t JS = 64 * VW;
     const int tid = threadIdx.x;
     const int64_t N = a.N;
+    const double c = moment_shift(a);
     double fin[2] = {0.0, 0.0};
     T *pvo = (T *)a.pv_out;
 #pragma unroll
@@ -1126,8 +1137,9 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
         for (int e = 0; e < VW; ++e) {
             const T v = pv[jj * VW + e];   // padded paths hold 0
             o.v[e] = v;
-            fin[0] += (double)v;
-            fin[1] += (double)v * (double)v;
+            const double d = (int64_t)(e0 + (uint32_t)jj * JS + (uint32_t)e) < N ? (double)v - c : 0.0;
+            fin[0] += d;
+            fin[1] += d * d;
         }
         *reinterpret_cast<Vec<T> *>(pvo + e0 + (uint32_t)jj * JS) = o;
     }
@@ -1140,9 +1152,9 @@ __device__ __forceinline__ void sweep_final(const SweepArgs &a, uint32_t gid, ui
     if (gid == 0) {
         if (tid == 0) {
             const double n = (double)N;
-            const double s1 = s_tot[0], s2 = s_tot[1];
-            const double mean = s1 / n;
-            double var = N > 1 ? (s2 - s1 * mean) / (n - 1.0) : 0.0;
+            const double s1 = s_tot[0], s2 = s_tot[1];   // about c
+            const double mean = c + s1 / n;
+            double var = N > 1 ? (s2 - s1 * (s1 / n)) / (n - 1.0) : 0.0;
             if (var < 0.0) var = 0.0;
             double price = mean, se = sqrt(var / n), t0 = 0.0;
             if (a.allow_exercise) {

@@ -1,6 +1,7 @@
 """GPU parity of the batched path: many options with uneven path and date
 counts in one generation launch and one persistent sweep.  Each option must
-match the FP64 oracle to the single-option tolerance, and be bitwise the same
+match the oracle to the single-option tolerance (FP32-bulk options that store
+binary32 paths: the oracle on binary32-rounded paths), and be bitwise the same
 priced alone (a batch of one) and in the mix."""
 import sys
 
@@ -36,11 +37,18 @@ def pricer(amq):
 def _small_mix(n=24, seed=7, dtype="fp64"):
     # The batch workload's distribution with fewer dates so the oracle is
     # quick.  FP64 runs also take path counts below the workload's 2^14 floor;
-    # FP32 runs stay at 2^14-2^15: there one exercise decision that rounds the
-    # other way moves a price by up to (largest payoff)/N, which passes the
-    # 2e-3 tolerance by itself once N is below about 2^12.
+    # FP32 runs stay at 2^14-2^15 (binary32 storage).
     lo, hi = (9.0, 13.0) if dtype == "fp64" else (14.0, 15.0)
     return batch_options(n, seed=seed, log2_paths=(lo, hi), dates=(3, 40))
+
+
+def _want(amq, orc, d, dtype, degree=2, store32=None):
+    """The oracle's price for one option of a batch priced in `dtype`."""
+    if store32 is None:
+        store32 = dtype == "fp32" and d["n_paths"] >= amq.AM_FP32_MIN_PATHS
+    return orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
+                              M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=degree,
+                              store32=store32)
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
@@ -52,8 +60,7 @@ def test_batch_matches_oracle(amq, orc, pricer, dtype):
     got = pricer.price_batch(opts, b, dtype)
     worst = 0.0
     for i, d in enumerate(specs):
-        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        want = _want(amq, orc, d, dtype)
         err = abs(got[i, 0] - want.price)
         worst = max(worst, err)
         assert err <= TOL[dtype], (i, d, got[i], want.price)
@@ -97,8 +104,7 @@ def test_batch_full_distribution_sample(amq, orc, pricer):
     got = pricer.price_batch(opts, b, "fp32")
     for i in (0, 17, 63):
         d = specs[i]
-        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        want = _want(amq, orc, d, "fp32")
         log(f"    opt {i}: N={d['n_paths']} M={d['n_dates']} gpu {got[i, 0]:.6f} oracle {want.price:.6f}")
         assert abs(got[i, 0] - want.price) <= TOL["fp32"]
 
@@ -114,10 +120,9 @@ def test_batch_autotune_and_graph_replay(amq, orc, pricer):
     log(f"  autotune: best ppt {best}, ms {ms}")
     assert best in (4, 16) and all(m > 0 for m in ms)
     tuned = pricer.price_batch(opts, b, "fp32")
-    # each tile shape is an FP32 result within tolerance of the FP64 oracle
+    # each tile shape is an FP32 result within tolerance of the oracle
     for i, d in enumerate(specs):
-        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        want = _want(amq, orc, d, "fp32")
         assert abs(ref[i, 0] - want.price) <= TOL["fp32"], (i, ref[i, 0], want.price)
         assert abs(tuned[i, 0] - want.price) <= TOL["fp32"], (i, tuned[i, 0], want.price)
     amq.am_debug_set_batch_ppt(16)
@@ -149,8 +154,7 @@ def test_batch_fp32_small_paths(amq, orc, pricer):
     got = pricer.price_batch(amq.make_options(specs), b, "fp32")
     worst = 0.0
     for i, d in enumerate(specs):
-        want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+        want = _want(amq, orc, d, "fp32")
         err = abs(got[i, 0] - want.price)
         worst = max(worst, err)
         assert err <= TOL["fp32"], (i, d, got[i], want.price)
@@ -158,3 +162,29 @@ def test_batch_fp32_small_paths(amq, orc, pricer):
     g64 = pricer.price_batch(amq.make_options([specs[i] for i in small]), b, "fp64")
     for j, i in enumerate(small):
         assert got[i, 0] == g64[j, 0] and got[i, 1] == g64[j, 1], i
+
+
+def test_batch_fp32_many_dates_ill_conditioned(amq, orc, pricer):
+    # options of the batch workload with 134-255 dates whose exercise
+    # decisions react to single-ulp changes of the binary32 path values
+    # (price moves of up to 7e-2 from a binary32 inverse normal).  Each must
+    # meet the oracle on binary32-stored paths; two of them sit farther than
+    # the tolerance from the all-binary64 oracle, which is the storage
+    # precision itself, not the kernels
+    full = batch_options(1024)
+    pick = [813, 105, 732, 18, 749]
+    specs = [full[i] for i in pick]
+    b = amq.make_basis("monomial", 2)
+    got = pricer.price_batch(amq.make_options(specs), b, "fp32")
+    for j, d in enumerate(specs):
+        want = _want(amq, orc, d, "fp32")
+        log(f"    opt {pick[j]}: N={d['n_paths']} M={d['n_dates']} gpu {got[j, 0]:.8f} "
+            f"oracle(binary32 paths) {want.price:.8f} |err| {abs(got[j, 0] - want.price):.2e}")
+        assert abs(got[j, 0] - want.price) <= TOL["fp32"], (pick[j], got[j], want.price)
+    # the same options on the single-option entry point
+    for j in (0, 3):
+        d = specs[j]
+        p = amq.make_params(d["S0"], d["K"], d["r"], d["sigma"], d["T"], d["is_call"])
+        single = pricer.price(p, d["n_paths"], d["n_dates"], b, "fp32")[0]
+        want = _want(amq, orc, d, "fp32")
+        assert abs(single - want.price) <= TOL["fp32"], (pick[j], single, want.price)

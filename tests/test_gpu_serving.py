@@ -66,7 +66,8 @@ def test_serving_mix_equals_alone_and_oracle(amq, orc, dtype):
     for i in range(0, 40, 3):
         d = specs[i]
         want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2,
+                                  store32=dtype == "fp32" and d["n_paths"] >= amq.AM_FP32_MIN_PATHS)
         assert mix[i]["status"] == 0
         assert abs(mix[i]["price"] - want.price) <= tol, (i, mix[i]["price"], want.price)
     lat = np.array([r["t_done"] - r["t_arrival"] for r in mix.values()])
@@ -86,7 +87,7 @@ def test_serving_refuses_request_larger_than_budget(amq):
 def test_serving_fp32_small_paths(amq, orc):
     # the served workload's lower path range, FP32 bulk: requests below
     # AM_FP32_MIN_PATHS paths run in a binary64 part of their batch; every
-    # result within the FP32-bulk tolerance of the oracle
+    # result within the FP32-bulk tolerance of the oracle on the same storage
     specs = batch_options(24, seed=31, log2_paths=(12.0, 14.6), dates=(12, 40))
     assert any(d["n_paths"] < amq.AM_FP32_MIN_PATHS for d in specs)
     b = amq.make_basis("monomial", 2)
@@ -98,7 +99,8 @@ def test_serving_fp32_small_paths(amq, orc):
     worst = 0.0
     for i, d in enumerate(specs):
         want = orc.price_american(d["S0"], d["K"], d["r"], d["sigma"], d["T"], N=d["n_paths"],
-                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2)
+                                  M=d["n_dates"], is_call=d["is_call"], kind=orc.MONOMIAL, degree=2,
+                                  store32=d["n_paths"] >= amq.AM_FP32_MIN_PATHS)
         assert got[i]["status"] == 0
         err = abs(got[i]["price"] - want.price)
         worst = max(worst, err)

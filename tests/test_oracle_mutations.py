@@ -40,14 +40,24 @@ MUTANTS = [
      "double drift = p->r + 0.5 * p->sigma * p->sigma;\n    for (int64_t c = 0; c < count; ++c) {"),
     ("origin not skipped", "uint64_t n = (uint64_t)(first + c) + 1u;       /* skip the origin */",
      "uint64_t n = (uint64_t)(first + c);"),
-    ("target not discounted", "double y = CF[i] * exp(-p->r * (t[tau[i]] - t[k]));", "double y = CF[i];"),
-    ("target discounted to t0", "double y = CF[i] * exp(-p->r * (t[tau[i]] - t[k]));",
-     "double y = CF[i] * exp(-p->r * t[tau[i]]);"),
-    ("out-of-the-money rows regressed", "if (!(h > 0.0)) continue;\n                or_basis_eval(kind, degree, row[i] / p->K, psi);\n                double y",
-     "or_basis_eval(kind, degree, row[i] / p->K, psi);\n                double y"),
-    ("exercise test reversed", "if (h > cont) { CF[i] = h; tau[i] = k; }", "if (h < cont) { CF[i] = h; tau[i] = k; }"),
+    ("target not discounted", ": CF[i] * exp(-p->r * (t[tau[i]] - t[k]));", ": CF[i];"),
+    ("target discounted to t0", ": CF[i] * exp(-p->r * (t[tau[i]] - t[k]));",
+     ": CF[i] * exp(-p->r * t[tau[i]]);"),
+    ("out-of-the-money rows regressed", "if (!(h > 0.0)) continue;\n                or_basis_eval(kind, degree, s / p->K, psi);\n                double y",
+     "or_basis_eval(kind, degree, s / p->K, psi);\n                double y"),
+    ("exercise test reversed", "if (h > cont) {\n                    CF[i] = h;", "if (h < cont) {\n                    CF[i] = h;"),
     ("first date never visited", "for (int k = M - 1; k >= 1; --k) {", "for (int k = M - 1; k >= 2; --k) {"),
-    ("pv discounted at maturity", "double pv = CF[i] * exp(-p->r * t[tau[i]]);", "double pv = CF[i] * exp(-p->r * p->T);"),
+    ("pv discounted at maturity", ": CF[i] * exp(-p->r * t[tau[i]]);", ": CF[i] * exp(-p->r * p->T);"),
+    ("store32 paths not rounded", "#define SV(x) (store32 ? rd32(x) : (x))", "#define SV(x) (x)"),
+    ("store32 cashflow not rounded", "if (store32) PV32[i] = rd32(h * exp(-p->r * t[k]));",
+     "if (store32) PV32[i] = h * exp(-p->r * t[k]);"),
+    ("store32 rounds before discounting", "if (store32) PV32[i] = rd32(h * exp(-p->r * t[k]));",
+     "if (store32) PV32[i] = rd32(h) * exp(-p->r * t[k]);"),
+    ("store32 terminal cashflow not rounded", "if (store32) PV32[i] = rd32(CF[i] * exp(-p->r * t[M]));",
+     "if (store32) PV32[i] = CF[i] * exp(-p->r * t[M]);"),
+    ("store32 target left at t0", "double y = store32 ? PV32[i] * exp(p->r * t[k])", "double y = store32 ? PV32[i]"),
+    ("store32 rounds toward zero", "static double rd32(double v) { return (double)(float)v; }",
+     "static double rd32(double v) { float f = (float)v; if (fabs((double)f) > fabs(v)) f = nextafterf(f, 0.0f); return (double)f; }"),
     ("givens rotation sign", "psi[l] = -s * t1 + c * t2;", "psi[l] = s * t1 + c * t2;"),
     ("back substitution index", "for (int l = j + 1; l < np; ++l) v -= R[j][l] * beta[l];",
      "for (int l = j + 1; l < np; ++l) v -= R[l][j] * beta[l];"),
@@ -100,6 +110,8 @@ def _pin_suite(orc):
         lambda: P.test_interpolating_regression_is_perfect_foresight(orc, 1, 3),
         lambda: P.test_hand_computed_two_path_case(orc),
         lambda: P.test_single_date_equals_exercise_off(orc),
+        lambda: P.test_store32_rounds_paths_and_cashflows_to_nearest(orc, False, 0, 2),
+        lambda: P.test_store32_exact_when_storage_is_exact(orc),
         lambda: P.test_exercise_off_matches_black_scholes(orc, c1, 1 << 12),
         lambda: P.test_exercise_off_matches_black_scholes(orc, c4, 1 << 12),
         lambda: P.test_laguerre_basis_matches_scipy(orc),

@@ -156,6 +156,57 @@ def test_homogeneity_is_bitwise(orc, call, kind, degree):
 
 
 # --------------------------------------------------------------------------
+# Binary32 storage: the induction on the path values rounded to binary32
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("call,kind,degree", [(False, 0, 2), (True, 0, 4), (False, 1, 3)])
+def test_store32_rounds_paths_and_cashflows_to_nearest(orc, call, kind, degree):
+    kw = dict(S0=100.0, K=104.0, r=0.06, sigma=0.3, T=1.0)
+    N, M = 3000, 12
+    S = orc.paths(**kw, N=N, M=M)
+    S32 = S.astype(np.float32).astype(np.float64)          # numpy's round to nearest
+    assert np.any(S32 != S)
+    # the full oracle in binary32 storage reads the paths rounded to nearest
+    got, gd = orc.price_american(**kw, N=N, M=M, is_call=call, kind=kind, degree=degree, store32=True,
+                                 detail=True)
+    on32, od = orc.lsm_on_paths(S32, **kw, is_call=call, kind=kind, degree=degree, store32=True, detail=True)
+    assert got.price == on32.price and np.array_equal(gd["pv"], od["pv"])
+    # every cashflow is its binary64 value discounted to t0, rounded to
+    # nearest: on the same (binary32) paths and the same stopping dates, the
+    # binary64-storage cashflow rounds to the binary32-storage one
+    full, fd = orc.lsm_on_paths(S32, **kw, is_call=call, kind=kind, degree=degree, detail=True)
+    same = od["tau"] == fd["tau"]
+    assert same.mean() >= 0.99
+    assert np.array_equal(od["pv"][same], fd["pv"][same].astype(np.float32).astype(np.float64))
+    # and the price moves at rounding level only
+    assert full.price != got.price and abs(full.price - got.price) < 1e-5
+
+
+def test_store32_exact_when_storage_is_exact(orc):
+    # r = 0 (no discounting) and path values already binary32 within [K/2, 2K]:
+    # every cashflow K - S is exact in binary32, so storage changes nothing
+    kw = dict(S0=100.0, K=104.0, r=0.0, sigma=0.1, T=1.0)
+    S = orc.paths(**kw, N=2000, M=9).astype(np.float32).astype(np.float64)
+    assert S.min() > 52.0 and S.max() < 208.0
+    a, ad = orc.lsm_on_paths(S, **kw, detail=True)
+    b, bd = orc.lsm_on_paths(S, **kw, detail=True, store32=True)
+    assert a.price == b.price and a.std_err == b.std_err and np.array_equal(ad["pv"], bd["pv"])
+    # sigma = 0 and r = 0: every path value is S0
+    c = orc.price_american(**dict(kw, sigma=0.0), N=500, M=7, allow_exercise=False, store32=True)
+    assert c.price == 4.0
+
+
+def test_store32_rqmc_replicates(orc):
+    kw = dict(S0=36.0, K=40.0, r=0.06, sigma=0.2, T=1.0)
+    sh = np.random.default_rng(5).integers(0, 2 ** 32, size=(2, 9), dtype=np.uint64).astype(np.uint32)
+    _, _, reps = orc.price_american_rqmc(**kw, N=2048, M=9, shifts=sh, store32=True)
+    for j in range(2):
+        one = orc.price_american_rqmc(**kw, N=2048, M=9, shifts=sh[j:j + 1], store32=True)[2][0]
+        assert one == reps[j]
+    _, _, reps64 = orc.price_american_rqmc(**kw, N=2048, M=9, shifts=sh)
+    assert np.all(reps != reps64) and np.abs(reps - reps64).max() < 1e-5
+
+
+# --------------------------------------------------------------------------
 # Levels: closed form without exercise, lattice with exercise
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("cfg,N", [(CONFIG1, 1 << 14), (CONFIG4, 1 << 14), (CONFIG2, 1 << 12)])
