@@ -43,10 +43,166 @@ namespace amq {
 #define AMQ_C7 0.0000002888167364
 #define AMQ_C8 0.0000003960315187
 
+// log(v) in binary64 for finite v > 0 (normal) by Tang's table method (P. T.
+// P. Tang, "Table-driven implementation of the logarithm function in IEEE
+// floating-point arithmetic", ACM TOMS 16(4), 1990): v = m 2^e with m in
+// [1/2, 1); F = 1/2 + j/256 + 1/512 from the top 7 fraction bits j of m, so
+// f = m - F is exact and |u| = |f / F| <= 2^-8; log v = e ln 2 + log F +
+// log1p(u), log1p by its Taylor series to degree 6 (truncation below 2e-18).
+// kLogTab[j] = {1/F, log F}, each rounded to nearest: 1/F by binary64
+// division, log F from a 50-digit decimal evaluation.  About 1 ulp for the
+// tail's arguments (results of magnitude 0.9 and more).
+__constant__ double kLogTab[128][2] = {
+    {0x1.fe01fe01fe020p+0, -0x1.60e52f45788e3p-1},
+    {0x1.fa11caa01fa12p+0, -0x1.5ced1e17c35c5p-1},
+    {0x1.f6310aca0dbb5p+0, -0x1.58fcddce004c4p-1},
+    {0x1.f25f644230ab5p+0, -0x1.55144fdbcbd62p-1},
+    {0x1.ee9c7f8458e02p+0, -0x1.513356667fc57p-1},
+    {0x1.eae807aba01ebp+0, -0x1.4d59d43fdaba2p-1},
+    {0x1.e741aa59750e4p+0, -0x1.4987ace0dabb0p-1},
+    {0x1.e3a9179dc1a73p+0, -0x1.45bcc464c893ap-1},
+    {0x1.e01e01e01e01ep+0, -0x1.41f8ff8471d61p-1},
+    {0x1.dca01dca01dcap+0, -0x1.3e3c43918f76cp-1},
+    {0x1.d92f2231e7f8ap+0, -0x1.3a86767257111p-1},
+    {0x1.d5cac807572b2p+0, -0x1.36d77e9d34fd7p-1},
+    {0x1.d272ca3fc5b1ap+0, -0x1.332f4314ad796p-1},
+    {0x1.cf26e5c44bfc6p+0, -0x1.2f8dab636337ap-1},
+    {0x1.cbe6d9601cbe7p+0, -0x1.2bf29f9841c3bp-1},
+    {0x1.c8b265afb8a42p+0, -0x1.285e0842ca384p-1},
+    {0x1.c5894d10d4986p+0, -0x1.24cfce6f80d9ap-1},
+    {0x1.c26b5392ea01cp+0, -0x1.2147dba47a394p-1},
+    {0x1.bf583ee868d8bp+0, -0x1.1dc619de06944p-1},
+    {0x1.bc4fd65883e7bp+0, -0x1.1a4a738b7a33cp-1},
+    {0x1.b951e2b18ff23p+0, -0x1.16d4d38c119fap-1},
+    {0x1.b65e2e3beee05p+0, -0x1.1365252bf0865p-1},
+    {0x1.b37484ad806cep+0, -0x1.0ffb54213a476p-1},
+    {0x1.b094b31d922a4p+0, -0x1.0c974c89431cep-1},
+    {0x1.adbe87f94905ep+0, -0x1.0938fae5d8e9bp-1},
+    {0x1.aaf1d2f87ebfdp+0, -0x1.05e04c1aa2c06p-1},
+    {0x1.a82e65130e159p+0, -0x1.028d2d6a963f4p-1},
+    {0x1.a574107688a4ap+0, -0x1.fe7f18eb03d3ep-2},
+    {0x1.a2c2a87c51ca0p+0, -0x1.f7eeae6b5761dp-2},
+    {0x1.a01a01a01a01ap+0, -0x1.f168f7fb05c52p-2},
+    {0x1.9d79f176b682dp+0, -0x1.eaedd2eac990cp-2},
+    {0x1.9ae24ea5510dap+0, -0x1.e47d1d32e677ep-2},
+    {0x1.9852f0d8ec0ffp+0, -0x1.de16b56ef90f0p-2},
+    {0x1.95cbb0be377aep+0, -0x1.d7ba7ad9e7da0p-2},
+    {0x1.934c67f9b2ce6p+0, -0x1.d1684d49f46aep-2},
+    {0x1.90d4f120190d5p+0, -0x1.cb200d2ceb643p-2},
+    {0x1.8e6527af1373fp+0, -0x1.c4e19b84723c2p-2},
+    {0x1.8bfce8062ff3ap+0, -0x1.beacd9e271ad1p-2},
+    {0x1.899c0f601899cp+0, -0x1.b881aa659bc93p-2},
+    {0x1.87427bcc092b9p+0, -0x1.b25fefb60cb2ep-2},
+    {0x1.84f00c2780614p+0, -0x1.ac478d020506fp-2},
+    {0x1.82a4a0182a4a0p+0, -0x1.a63865fabd0ecp-2},
+    {0x1.8060180601806p+0, -0x1.a0325ed14fda4p-2},
+    {0x1.7e225515a4f1dp+0, -0x1.9a355c33bd6bap-2},
+    {0x1.7beb3922e017cp+0, -0x1.9441434a03259p-2},
+    {0x1.79baa6bb6398bp+0, -0x1.8e55f9b349b83p-2},
+    {0x1.77908119ac60dp+0, -0x1.8873658327ccfp-2},
+    {0x1.756cac201756dp+0, -0x1.82996d3ef8bcbp-2},
+    {0x1.734f0c541fe8dp+0, -0x1.7cc7f7db46a0ep-2},
+    {0x1.713786d9c7c09p+0, -0x1.76feecb947175p-2},
+    {0x1.6f26016f26017p+0, -0x1.713e33a46a17cp-2},
+    {0x1.6d1a62681c861p+0, -0x1.6b85b4cffa3fdp-2},
+    {0x1.6b1490aa31a3dp+0, -0x1.65d558d4ce00bp-2},
+    {0x1.691473a88d0c0p+0, -0x1.602d08af091ecp-2},
+    {0x1.6719f3601671ap+0, -0x1.5a8cadbbedfa1p-2},
+    {0x1.6524f853b4aa3p+0, -0x1.54f431b7be1a9p-2},
+    {0x1.63356b88ac0dep+0, -0x1.4f637ebba9810p-2},
+    {0x1.614b36831ae94p+0, -0x1.49da7f3bcc41fp-2},
+    {0x1.5f66434292dfcp+0, -0x1.44591e0539f49p-2},
+    {0x1.5d867c3ece2a5p+0, -0x1.3edf463c1683ep-2},
+    {0x1.5babcc647fa91p+0, -0x1.396ce359bbf54p-2},
+    {0x1.59d61f123ccaap+0, -0x1.3401e12aecba1p-2},
+    {0x1.5805601580560p+0, -0x1.2e9e2bce12286p-2},
+    {0x1.56397ba7c52e2p+0, -0x1.2941afb186b7cp-2},
+    {0x1.54725e6bb82fep+0, -0x1.23ec5991eba49p-2},
+    {0x1.52aff56a8054bp+0, -0x1.1e9e1678899f4p-2},
+    {0x1.50f22e111c4c5p+0, -0x1.1956d3b9bc2fap-2},
+    {0x1.4f38f62dd4c9bp+0, -0x1.14167ef367783p-2},
+    {0x1.4d843bedc2c4cp+0, -0x1.0edd060b78081p-2},
+    {0x1.4bd3edda68fe1p+0, -0x1.09aa572e6c6d4p-2},
+    {0x1.4a27fad76014ap+0, -0x1.047e60cde83b8p-2},
+    {0x1.4880522014880p+0, -0x1.feb2233ea07cdp-3},
+    {0x1.46dce34596066p+0, -0x1.f474b134df229p-3},
+    {0x1.453d9e2c776cap+0, -0x1.ea4449f04aaf5p-3},
+    {0x1.43a2730abee4dp+0, -0x1.e020cc6235ab5p-3},
+    {0x1.420b5265e5951p+0, -0x1.d60a17f903515p-3},
+    {0x1.40782d10e6566p+0, -0x1.cc000c9db3c52p-3},
+    {0x1.3ee8f42a5af07p+0, -0x1.c2028ab17f9b4p-3},
+    {0x1.3d5d991aa75c6p+0, -0x1.b811730b823d2p-3},
+    {0x1.3bd60d9232955p+0, -0x1.ae2ca6f672bd4p-3},
+    {0x1.3a524387ac822p+0, -0x1.a454082e6ab05p-3},
+    {0x1.38d22d366088ep+0, -0x1.9a8778debaa38p-3},
+    {0x1.3755bd1c945eep+0, -0x1.90c6db9fcbcd9p-3},
+    {0x1.35dce5f9f2af8p+0, -0x1.871213750e994p-3},
+    {0x1.34679ace01346p+0, -0x1.7d6903caf5ad0p-3},
+    {0x1.32f5ced6a1dfap+0, -0x1.73cb9074fd14dp-3},
+    {0x1.3187758e9ebb6p+0, -0x1.6a399dabbd383p-3},
+    {0x1.301c82ac40260p+0, -0x1.60b3100b09476p-3},
+    {0x1.2eb4ea1fed14bp+0, -0x1.5737cc9018cddp-3},
+    {0x1.2d50a012d50a0p+0, -0x1.4dc7b897bc1c8p-3},
+    {0x1.2bef98e5a3711p+0, -0x1.4462b9dc9b3dcp-3},
+    {0x1.2a91c92f3c105p+0, -0x1.3b08b6757f2a9p-3},
+    {0x1.293725bb804a5p+0, -0x1.31b994d3a4f85p-3},
+    {0x1.27dfa38a1ce4dp+0, -0x1.28753bc11aba5p-3},
+    {0x1.268b37cd60127p+0, -0x1.1f3b925f25d41p-3},
+    {0x1.2539d7e9177b2p+0, -0x1.160c8024b27b1p-3},
+    {0x1.23eb79717605bp+0, -0x1.0ce7ecdccc28dp-3},
+    {0x1.22a0122a0122ap+0, -0x1.03cdc0a51ec0dp-3},
+    {0x1.21579804855e6p+0, -0x1.f57bc7d9005dbp-4},
+    {0x1.2012012012012p+0, -0x1.e3707ee30487bp-4},
+    {0x1.1ecf43c7fb84cp+0, -0x1.d179788219364p-4},
+    {0x1.1d8f5672e4abdp+0, -0x1.bf968769fca11p-4},
+    {0x1.1c522fc1ce059p+0, -0x1.adc77ee5aea8cp-4},
+    {0x1.1b17c67f2bae3p+0, -0x1.9c0c32d4d2548p-4},
+    {0x1.19e0119e0119ep+0, -0x1.8a6477a91dc29p-4},
+    {0x1.18ab083902bdbp+0, -0x1.78d02263d82d3p-4},
+    {0x1.1778a191bd684p+0, -0x1.674f089365a7ap-4},
+    {0x1.1648d50fc3201p+0, -0x1.55e10050e0384p-4},
+    {0x1.151b9a3fdd5c9p+0, -0x1.4485e03dbdfadp-4},
+    {0x1.13f0e8d344724p+0, -0x1.333d7f8183f4bp-4},
+    {0x1.12c8b89edc0acp+0, -0x1.2207b5c78549ep-4},
+    {0x1.11a3019a74826p+0, -0x1.10e45b3cae831p-4},
+    {0x1.107fbbe011080p+0, -0x1.ffa6911ab9301p-5},
+    {0x1.0f5edfab325a2p+0, -0x1.dda8adc67ee4ep-5},
+    {0x1.0e40655826011p+0, -0x1.bbcebfc68f420p-5},
+    {0x1.0d24456359e3ap+0, -0x1.9a187b573de7cp-5},
+    {0x1.0c0a7868b4171p+0, -0x1.788595a3577bap-5},
+    {0x1.0af2f722eecb5p+0, -0x1.5715c4c03ceefp-5},
+    {0x1.09ddba6af8360p+0, -0x1.35c8bfaa1306bp-5},
+    {0x1.08cabb37565e2p+0, -0x1.149e3e4005a8dp-5},
+    {0x1.07b9f29b8eae2p+0, -0x1.e72bf2813ce51p-6},
+    {0x1.06ab59c7912fbp+0, -0x1.a55f548c5c43fp-6},
+    {0x1.059eea0727586p+0, -0x1.63d6178690bd6p-6},
+    {0x1.04949cc1664c5p+0, -0x1.228fb1fea2e28p-6},
+    {0x1.038c6b78247fcp+0, -0x1.c317384c75f06p-7},
+    {0x1.02864fc7729e9p+0, -0x1.41929f96832f0p-7},
+    {0x1.0182436517a37p+0, -0x1.8121214586b54p-8},
+    {0x1.0080402010080p+0, -0x1.0040155d5889ep-9},
+};
+
+__device__ __forceinline__ double log_tab(double v)
+{
+    const double m = __builtin_amdgcn_frexp_mant(v);
+    const int e = __builtin_amdgcn_frexp_exp(v);
+    const uint32_t j = (uint32_t)((uint64_t)__double_as_longlong(m) >> 45) & 127u;
+    const double F = fma((double)j, 0x1p-8, 0.5 + 0x1p-9);
+    const double u = (m - F) * kLogTab[j][0];
+    double p = fma(u, -1.0 / 6.0, 0.2);
+    p = fma(p, u, -0.25);
+    p = fma(p, u, 1.0 / 3.0);
+    p = fma(p, u, -0.5);
+    const double l1p = fma(p, u * u, u);
+    const double de = (double)e;
+    return fma(de, 0.69314718055994529, fma(de, 2.3190468138462996e-17, kLogTab[j][1] + l1p));
+}
+
 // The two branches separately: which branch a point takes, the central
-// rational function and the tail polynomial (its two logarithms by log_f64,
-// about 1 ulp).  inv_normal_f64 combines them; the path generator evaluates
-// the tails packed.
+// rational function and the tail polynomial (its two logarithms by
+// log_tab).  inv_normal_f64 combines them; the path generator evaluates the
+// tails packed.
 template <typename T> struct MoroParts;
 
 template <> struct MoroParts<double> {
@@ -82,7 +238,7 @@ template <> struct MoroParts<double> {
         const double s = 0x1p-32;
         const double y = ((double)x - 2147483648.0) * s;
         const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
-        const double t = log_f64(-log_f64(q));
+        const double t = log_tab(-log_tab(q));
         double v = AMQ_C8;
         v = v * t + AMQ_C7;
         v = v * t + AMQ_C6;
@@ -115,7 +271,7 @@ __device__ __forceinline__ double inv_normal_mid_f64(uint32_t x)
         return num / den;
     }
     const double q = y < 0.0 ? ((double)x + 0.5) * s : (4294967296.0 - (double)x - 0.5) * s;
-    const double t = log_f64(-log_f64(q));
+    const double t = log_tab(-log_tab(q));
     double v = AMQ_C8;
     v = v * t + AMQ_C7;
     v = v * t + AMQ_C6;

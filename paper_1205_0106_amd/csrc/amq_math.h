@@ -93,39 +93,4 @@ __device__ __forceinline__ double rcp_f64(double d)
     return y;
 }
 
-// log(v) in binary64 for finite v > 0 (normal): v = m 2^e with m in
-// [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f / (2 + f), and
-// log(1 + f) = 2 atanh(s) = f - f^2/2 + s (f^2/2 + R(s^2)) with
-// R(z) = sum_{k>=1} 2 z^k / (2k + 1), the Taylor series of the odd part (the
-// classic libm reduction, e.g. Sun's fdlibm e_log.c, with the series in place
-// of its minimax fit).  |s| <= 0.1716, so ten terms leave a truncation below
-// 1e-18 relative; the reciprocal error enters only through s (f^2/2 + R).
-// log(v) = e ln 2 + log(1 + f), with ln 2 split into head and tail.
-__device__ __forceinline__ double log_f64(double v)
-{
-    double m = __builtin_amdgcn_frexp_mant(v);          // [1/2, 1)
-    int e = __builtin_amdgcn_frexp_exp(v);              // v = m 2^e
-    const bool lo = m < 0.70710678118654752;
-    m = lo ? m + m : m;
-    e = lo ? e - 1 : e;
-    const double f = m - 1.0;
-    const double s = f * rcp_f64(2.0 + f);
-    const double z = s * s;
-    double R = 2.0 / 21.0;
-    R = fma(R, z, 2.0 / 19.0);
-    R = fma(R, z, 2.0 / 17.0);
-    R = fma(R, z, 2.0 / 15.0);
-    R = fma(R, z, 2.0 / 13.0);
-    R = fma(R, z, 2.0 / 11.0);
-    R = fma(R, z, 2.0 / 9.0);
-    R = fma(R, z, 2.0 / 7.0);
-    R = fma(R, z, 2.0 / 5.0);
-    R = fma(R, z, 2.0 / 3.0);
-    R = R * z;
-    const double hfsq = 0.5 * f * f;
-    const double lm = f - (hfsq - s * (hfsq + R));
-    const double de = (double)e;
-    return fma(de, 0.69314718055994529, fma(de, 2.3190468138462996e-17, lm));
-}
-
 }  // namespace amq

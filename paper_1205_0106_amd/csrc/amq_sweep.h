@@ -376,7 +376,7 @@ template <int D>
 __device__ __forceinline__ void solve_date_wave(const double *tot, double *beta, double (*s_col)[8])
 {
     constexpr int P = D + 1, NA = 2 * D + 1;
-    const int lane = threadIdx.x & 63;
+    const int lane = tid_x() & 63;
     const int i = lane < P ? lane : P - 1;
     const double n = rint(tot[NA + P]);
     const double dii = tot[2 * i];
@@ -444,7 +444,7 @@ __device__ __forceinline__ void solve_and_record_wave(const SweepArgs &a, uint32
     constexpr int NV = 3 * D + 4;
     const uint64_t c_all = __builtin_amdgcn_s_memrealtime();
     solve_date_wave<D>(s_tot, s_beta, s_col);
-    if (gid == 0 && threadIdx.x == 0) {
+    if (gid == 0 && tid_x() == 0) {
         double *rec = a.rec + (size_t)k * kRec;
 #pragma unroll
         for (int q = 0; q < 10; ++q) rec[q] = s_beta[q];

@@ -6,6 +6,20 @@
 
 namespace amq {
 
+// threadIdx.x through an empty asm: a value the compiler cannot share across
+// calls.  The helpers below run once per date inside the sweeps' date loops;
+// with their per-lane indexes and addresses derived from it, those are
+// recomputed at each call (a few instructions) instead of being hoisted out
+// of the loop and held in registers, or spilled to scratch memory and
+// reloaded on the date's critical path, in kernels whose registers hold
+// path data.
+__device__ __forceinline__ uint32_t tid_x()
+{
+    uint32_t t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -82,7 +96,8 @@ __device__ __forceinline__ double add_halves32(double x)
 template <int NV, int NU = 0, int WG = kWG>
 __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t tx = tid_x();
+    const int lane = tx & 63, wave = tx >> 6;
 #pragma unroll
     for (int q = 0; q < NV - NU; ++q) v[q] = wave_sum(v[q]);
     if (lane == 63) {
@@ -90,7 +105,7 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
         for (int q = 0; q < NV; ++q) s_red[wave][q] = v[q];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tx == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             double t = s_red[0][q];
@@ -111,9 +126,10 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double (*s_red)[32])
 template <int NV, int NU, int WG>
 __device__ __forceinline__ void group_sum_lds(double (&v)[NV], double *s_x, double (*s_red)[32])
 {
+    const uint32_t tx = tid_x();
     constexpr int NC = NV - NU, TPC = WG / 8;
     static_assert(NC <= 8 && NV <= 32 && (TPC == 32 || TPC == 64), "component slots");
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = tx, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int q = 0; q < NC; ++q) s_x[q * WG + tid] = v[q];
     if (lane == 63) {
@@ -162,7 +178,8 @@ __device__ __forceinline__ void group_sum_lds(double (&v)[NV], double *s_x, doub
 template <int NV>
 __device__ void reduce_partials(const double *part, uint32_t G, double *tot, double (*s_red8)[32])
 {
-    const int c = threadIdx.x & 31, sgrp = threadIdx.x >> 5;   // 8 groups of 32
+    const uint32_t tx = tid_x();
+    const int c = tx & 31, sgrp = tx >> 5;   // 8 groups of 32
     double v = 0.0;
     if (c < NV) {
         for (uint32_t g0 = sgrp; g0 < G; g0 += 8 * 4) {
@@ -178,11 +195,11 @@ __device__ void reduce_partials(const double *part, uint32_t G, double *tot, dou
     }
     s_red8[sgrp][c] = v;
     __syncthreads();
-    if (threadIdx.x < NV) {
+    if (tx < NV) {
         double t = 0.0;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) t += s_red8[s][threadIdx.x];
-        tot[threadIdx.x] = t;
+        for (int s = 0; s < 8; ++s) t += s_red8[s][tx];
+        tot[tx] = t;
     }
     __syncthreads();
 }
@@ -234,6 +251,7 @@ template <int NV, int RW, int WG, typename OnMiss>
 __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t tag, uint32_t *err,
                                 uint32_t limit, double *tot, double (*s_red)[32], int *s_flag, OnMiss on_miss)
 {
+    const uint32_t tx = tid_x();
     static_assert(RW == 16 || RW == 32, "row width");
     constexpr int NW = WG / 64;
     constexpr uint32_t RP = WG / RW;    // rows per pass
@@ -241,8 +259,8 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
     // their cashflows and slab values in registers meanwhile).  The order in
     // which a thread adds its rows does not depend on it.
     constexpr int KB = WG >= 512 ? 8 : 16;
-    const uint32_t c = threadIdx.x % RW, rs = threadIdx.x / RW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t c = tx % RW, rs = tx / RW;
+    const int lane = tx & 63, wave = tx >> 6;
     uint32_t it = 0;
     for (;;) {
         double acc = 0.0;
@@ -273,17 +291,17 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
 #pragma unroll
         for (int q = 0; q < NW; ++q) anybad |= s_flag[1 + q] != 0;
         if (!anybad) {
-            if (threadIdx.x < NV) {
+            if (tx < NV) {
                 double t = 0.0;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) t += s_red[q][threadIdx.x];
-                tot[threadIdx.x] = t;
+                for (int q = 0; q < NW; ++q) t += s_red[q][tx];
+                tot[tx] = t;
             }
             __syncthreads();
             return true;
         }
         if (++it > limit) {
-            if (threadIdx.x == 0) raise_error(err);
+            if (tx == 0) raise_error(err);
             return false;
         }
         if (!on_miss(it)) return false;
@@ -294,7 +312,8 @@ __device__ inline bool sum_rows(const uint64_t *slots, uint32_t count, uint64_t 
 // group has raised the error word.  Collective.
 __device__ inline bool rows_backoff(uint32_t *err, int *s_flag)
 {
-    if (threadIdx.x == 0) s_flag[0] = ld_agent(err) != 0u ? 1 : 0;
+    const uint32_t tx = tid_x();
+    if (tx == 0) s_flag[0] = ld_agent(err) != 0u ? 1 : 0;
     __builtin_amdgcn_s_sleep(1);
     __syncthreads();
     return s_flag[0] == 0;
@@ -326,6 +345,7 @@ __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, ui
                                          uint32_t *words, uint32_t *err, uint32_t epoch, uint32_t limit,
                                          double *tot, double (*s_red)[32], int *s_flag)
 {
+    const uint32_t tx = tid_x();
     static_assert(NV <= RW && RW <= 32 && (RW & (RW - 1)) == 0, "row width");
     const uint64_t tag = epoch & 3u;
     uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
@@ -333,16 +353,16 @@ __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, ui
     const uint32_t TS = team_size(G);
     const uint32_t tau = gid / TS;
     const bool flat = G <= kFlatMaxGroups;
-    if (threadIdx.x == 0) put_row<NV>(slots + (size_t)gid * RW, v, tag);
+    if (tx == 0) put_row<NV>(slots + (size_t)gid * RW, v, tag);
     if (flat) {
         // the counter's old value is not used: nothing waits for the round trip
-        if (threadIdx.x == 0)
+        if (tx == 0)
             (void)__hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     } else {
         // team level: the team's last arriver sums its team's rows in member
         // order and publishes the team row (tagged like the group rows)
-        if (threadIdx.x == 0) {
+        if (tx == 0) {
             const uint32_t old = __hip_atomic_fetch_add(words + kSyncLine * (1 + tau), 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             s_flag[1 + WG / 64] = old + 1u == epoch * min(TS, G - tau * TS) ? 1 : 0;
@@ -353,7 +373,7 @@ __device__ inline bool allreduce_publish(const double (&v)[NV], uint32_t gid, ui
             if (!sum_rows<NV, RW, WG>(slots + (size_t)first * RW, min(TS, G - first), tag, err, limit, tot, s_red,
                                       s_flag, [&](uint32_t) { return rows_backoff(err, s_flag); }))
                 return false;
-            if (threadIdx.x == 0) put_row<NV>(tslots + (size_t)tau * RW, tot, tag);
+            if (tx == 0) put_row<NV>(tslots + (size_t)tau * RW, tot, tag);
         }
     }
     return true;
@@ -371,17 +391,18 @@ __device__ inline bool allreduce_gather(uint32_t G, uint64_t *rows, uint32_t *wo
                                         uint32_t epoch, uint32_t limit, double *tot, double (*s_red)[32],
                                         int *s_flag, bool rows_first = false)
 {
+    const uint32_t tx = tid_x();
     const uint64_t tag = epoch & 3u;
     uint64_t *slots = rows + (size_t)(epoch & 1u) * G * RW;
     uint64_t *tslots = rows + (size_t)2 * G * RW + (size_t)(epoch & 1u) * kMaxTeams * RW;
     const uint32_t TS = team_size(G), NT = (G + TS - 1) / TS;
     const bool flat = G <= kFlatMaxGroups;
     auto poll = [&]() -> bool {
-        if (threadIdx.x < 64) {
+        if (tx < 64) {
             // flat: lane t < NT watches team t's counter; teams: lane t
             // watches team t's row (word 0 carries the epoch tag).
             // Wave-uniform exit.
-            const uint32_t lane = threadIdx.x;
+            const uint32_t lane = tx;
             const uint32_t want = lane < NT ? min(TS, G - lane * TS) * epoch : 0u;
             uint32_t it = 0;
             bool ok = true;
