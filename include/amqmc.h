@@ -116,10 +116,11 @@ size_t am_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int3
  *       holds the date's regression: [0..7] coefficients of the fitted value
  *       (cashflow discounted to t0) in the engine's standardised basis, [8] 1
  *       if solved / 0 if the date allowed no exercise, [9] in-the-money count,
- *       [10..30] the moment sums it was solved from, [32..37] device clock
- *       stamps (100 MHz) of the date's phases: last arrival seen, partials
- *       summed, solved, group 0 arrived, group 0 released, group 0 started
- *       its reduction;
+ *       [10..30] the moment sums it was solved from, [32..36] group 0's
+ *       device clock stamps (100 MHz) of the date's phases: moments summed
+ *       in the group, device-wide totals in hand, solved, the next date's
+ *       Gram part summed (tiles that overlap it with the sum; else equal to
+ *       [32]), the date's pass started;
  *   [3] result: [8] double {price, std_err, mean_pv, t0_exercise, n_skipped,
  *       error_flag, 0, 0};
  *   [4] ld (elements, not bytes); [5] total bytes.
