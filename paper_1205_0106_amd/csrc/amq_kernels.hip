@@ -183,20 +183,29 @@ __constant__ double kLogTab[128][2] = {
     {0x1.0080402010080p+0, -0x1.0040155d5889ep-9},
 };
 
-__device__ __forceinline__ double log_tab(double v)
+// logF: the table's log F column, from constant memory or from an LDS copy
+// (the path generator's: its loads then wait on LDS only, not on the
+// generator's pending stores); 1/F by the reciprocal's Newton refinement.
+template <typename LogF>
+__device__ __forceinline__ double log_tab(double v, LogF logF)
 {
     const double m = __builtin_amdgcn_frexp_mant(v);
     const int e = __builtin_amdgcn_frexp_exp(v);
     const uint32_t j = (uint32_t)((uint64_t)__double_as_longlong(m) >> 45) & 127u;
     const double F = fma((double)j, 0x1p-8, 0.5 + 0x1p-9);
-    const double u = (m - F) * kLogTab[j][0];
+    const double u = (m - F) * rcp_f64(F);
     double p = fma(u, -1.0 / 6.0, 0.2);
     p = fma(p, u, -0.25);
     p = fma(p, u, 1.0 / 3.0);
     p = fma(p, u, -0.5);
     const double l1p = fma(p, u * u, u);
     const double de = (double)e;
-    return fma(de, 0.69314718055994529, fma(de, 2.3190468138462996e-17, kLogTab[j][1] + l1p));
+    return fma(de, 0.69314718055994529, fma(de, 2.3190468138462996e-17, logF(j) + l1p));
+}
+
+__device__ __forceinline__ double log_tab(double v)
+{
+    return log_tab(v, [](uint32_t j) { return kLogTab[j][1]; });
 }
 
 // The two branches separately: which branch a point takes, the central
@@ -233,12 +242,13 @@ template <> struct MoroParts<double> {
                                D, 1.0);
         return num * rcp_f64(den);   // (a tail point's value is discarded)
     }
-    static __device__ __forceinline__ double tail_value(uint32_t x)
+    template <typename LogF>
+    static __device__ __forceinline__ double tail_value(uint32_t x, LogF logF)
     {
         const double s = 0x1p-32;
         const double y = ((double)x - 2147483648.0) * s;
         const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
-        const double t = log_tab(-log_tab(q));
+        const double t = log_tab(-log_tab(q, logF), logF);
         double v = AMQ_C8;
         v = v * t + AMQ_C7;
         v = v * t + AMQ_C6;
@@ -249,6 +259,10 @@ template <> struct MoroParts<double> {
         v = v * t + AMQ_C1;
         v = v * t + AMQ_C0;
         return y < 0.0 ? -v : v;
+    }
+    static __device__ __forceinline__ double tail_value(uint32_t x)
+    {
+        return tail_value(x, [](uint32_t j) { return kLogTab[j][1]; });
     }
 };
 
@@ -304,10 +318,11 @@ __host__ __device__ size_t generate_lds_bytes(int M, int fp64)
 {
     // lane tables [M][16], per-wave block words [kWaves][M][2], per-wave tail
     // staging: points [kTailChunk * 64] u32 and normals [kTailChunk * 64] f64
-    // (both storage types: the normals are binary64)
+    // (both storage types: the normals are binary64), the logarithm table's
+    // log F column [128] f64
     (void)fp64;
     return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t) +
-           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8;
+           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 + 128 * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,10 +356,13 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
     // this wave's tail staging (see kTailChunk)
     uint32_t *tx = lds + (size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)wave * kTailChunk * 64;
-    double *tz = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) +
+    double *tz0 = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) +
                                   (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * kTailChunk * 64) *
-                                       sizeof(uint32_t) + 7) / 8 * 8) +
-            (size_t)wave * kTailChunk * 64;
+                                       sizeof(uint32_t) + 7) / 8 * 8);
+    double *tz = tz0 + (size_t)wave * kTailChunk * 64;
+    // the logarithm table's log F column, for the packed tails
+    double *ltab = tz0 + (size_t)kWaves * kTailChunk * 64;
+    for (int j = tid; j < 128; j += kWG) ltab[j] = kLogTab[j][1];
 
     if (init && WHAT == 0) {
         for (int q = tid; q < kSyncWords; q += kWG) a.sync[q] = 0u;
@@ -480,7 +498,8 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 for (uint32_t t0 = 0; t0 < ntail; t0 += 64) {
                     const uint32_t t = t0 + (uint32_t)lane;
-                    if (t < ntail) tz[t] = MoroParts<double>::tail_value(tx[t]);
+                    if (t < ntail)
+                        tz[t] = MoroParts<double>::tail_value(tx[t], [=](uint32_t j) { return ltab[j]; });
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
