@@ -277,13 +277,27 @@ def variant_run(args):
     dt = time.perf_counter() - t0
     res = call(True)
     total = (n_paths * (args.rqmc or 1)) * w.n_dates
-    return {"metric": "path-steps/s for QMC American pricing (" + ("paper estimator" if args.paper_estimator
-                                                                   else "randomised QMC-LSM") + ")",
-            "value": total * args.steps / dt, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
-            "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64", "data": "synthetic (on-device Sobol paths)",
-            "config": {"workload": w.name, "variant": what, "path_steps": total},
-            "price": float(res[0]), "error_bar": float(res[1])}
+    out = {"metric": "path-steps/s for QMC American pricing (" + ("paper estimator" if args.paper_estimator
+                                                                  else "randomised QMC-LSM") + ")",
+           "value": total * args.steps / dt, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+           "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64", "data": "synthetic (on-device Sobol paths)",
+           "config": {"workload": w.name, "variant": what, "path_steps": total},
+           "price": float(res[0]), "error_bar": float(res[1])}
+    if args.rqmc:
+        # the replicates one after another, for comparison with the batch form above
+        serial = lambda: pr.price_rqmc(p, n_paths, w.n_dates, b, dtype, shifts, fused=False)
+        for _ in range(args.warmup):
+            serial()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rs = serial()
+        torch.cuda.synchronize()
+        ds = time.perf_counter() - t0
+        out["replicates_one_after_another"] = {"value": total * args.steps / ds, "ms_per_step": 1e3 * ds / args.steps,
+                                               "price": float(rs[0]), "error_bar": float(rs[1])}
+    return out
 
 
 def cpu_model():

@@ -184,11 +184,27 @@ int am_price_american_noalloc(const am_params *params, int64_t n_paths, int32_t 
  * uniform 32-bit words) mapped to cell midpoints u = (x + 1/2) 2^-32.
  * h_out (n_rep + 2 doubles, or NULL for asynchronous use) receives the mean
  * of the replicate prices, sd/sqrt(n_rep) across replicates (an honest
- * error bar), then the replicate prices.  1 <= n_rep <= 64.  Workspace as in
+ * error bar), then the replicate prices.  1 <= n_rep <= 64.  The replicates
+ * run one after another in the single-option layout; workspace as in
  * am_price_american_ex. */
 int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates,
                            am_basis basis, int32_t dtype, int32_t n_rep, const uint32_t *h_shifts,
                            void *d_workspace, size_t ws_bytes, void *hip_stream, double *h_out);
+
+/* The same replicates all at once: a batch of identical options, each with
+ * its own digital shift (one generation launch and one persistent sweep, as
+ * am_price_batch), the mean and error bar formed on the host in the order
+ * and arithmetic of am_price_american_rqmc's final step.  Replicate prices
+ * agree with am_price_american_rqmc's to rounding (the tiles sum in a
+ * different order).  Workspace: am_rqmc_workspace_bytes, 256-byte aligned;
+ * h_out (n_rep + 2 doubles) is required; returns once the results are in. */
+int am_price_rqmc_batch(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                        int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
+                        size_t ws_bytes, void *hip_stream, double *h_out);
+
+/* Workspace bytes of am_price_rqmc_batch (0 if the arguments are invalid). */
+size_t am_rqmc_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype,
+                               int32_t n_rep);
 
 /* The paper's own estimator (Section V, eqs. (10)-(11)) on the same
  * quasi-random paths: n_points exercise points t_i = i T/(n_points+1); at the

@@ -123,6 +123,10 @@ def lib():
         L.am_price_paper_estimator.argtypes = [P(am_params), i64, i32, i32, ctypes.c_void_p, sz,
                                                ctypes.c_void_p, P(dbl)]
         L.am_price_paper_estimator.restype = ctypes.c_int
+        L.am_price_rqmc_batch.argtypes = L.am_price_american_rqmc.argtypes
+        L.am_price_rqmc_batch.restype = ctypes.c_int
+        L.am_rqmc_workspace_bytes.argtypes = [i64, i32, am_basis, i32, i32]
+        L.am_rqmc_workspace_bytes.restype = sz
         L.am_batch_workspace_bytes.argtypes = [P(am_option), i32, am_basis, i32]
         L.am_batch_workspace_bytes.restype = sz
         L.am_price_batch.argtypes = [P(am_option), i32, am_basis, i32, ctypes.c_void_p, sz,
@@ -275,9 +279,9 @@ def am_price_american_noalloc(params: am_params, n_paths: int, n_dates: int, bas
 
 
 def am_price_american_rqmc(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
-                           shifts, workspace, stream=None):
-    """Randomised QMC (digital shifts, uint32 [R][n_dates]); returns
-    (mean, error bar, replicate prices)."""
+                           shifts, workspace, stream=None, _entry="am_price_american_rqmc"):
+    """Randomised QMC (digital shifts, uint32 [R][n_dates]), replicates one
+    after another; returns (mean, error bar, replicate prices)."""
     import numpy as np
     import torch
     if stream is None:
@@ -285,11 +289,24 @@ def am_price_american_rqmc(params: am_params, n_paths: int, n_dates: int, basis:
     sh = np.ascontiguousarray(shifts, dtype=np.uint32)
     R = sh.shape[0]
     out = (ctypes.c_double * (R + 2))()
-    _check(lib().am_price_american_rqmc(ctypes.byref(params), int(n_paths), int(n_dates), basis,
-                                        _dtype(dtype), R, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                                        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                        ctypes.c_void_p(stream.cuda_stream), out))
+    _check(getattr(lib(), _entry)(ctypes.byref(params), int(n_paths), int(n_dates), basis,
+                                  _dtype(dtype), R, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                  ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                  ctypes.c_void_p(stream.cuda_stream), out))
     return out[0], out[1], np.array(out[2:R + 2])
+
+
+def am_price_rqmc_batch(params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype,
+                        shifts, workspace, stream=None):
+    """The same replicates all at once (batch form); returns (mean, error bar,
+    replicate prices)."""
+    return am_price_american_rqmc(params, n_paths, n_dates, basis, dtype, shifts, workspace, stream,
+                                  _entry="am_price_rqmc_batch")
+
+
+def am_rqmc_workspace_bytes(n_paths: int, n_dates: int, basis: am_basis, dtype, n_rep: int) -> int:
+    """Workspace of the all-replicates-at-once randomised QMC form (0: invalid)."""
+    return int(lib().am_rqmc_workspace_bytes(int(n_paths), int(n_dates), basis, _dtype(dtype), int(n_rep)))
 
 
 def am_price_paper_estimator(params: am_params, n_paths: int, n_points: int, dtype, workspace,
@@ -518,10 +535,18 @@ class Pricer:
         ws = self.workspace(nbytes)
         return am_price_american_ex(params, n_paths, n_dates, basis, dtype, ws, self.stream, wait)
 
-    def price_rqmc(self, params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype, shifts):
+    def price_rqmc(self, params: am_params, n_paths: int, n_dates: int, basis: am_basis, dtype, shifts,
+                   fused: bool = True):
+        """fused: every replicate at once (batch form); else one after another."""
+        if fused:
+            nbytes = am_rqmc_workspace_bytes(n_paths, n_dates, basis, dtype, len(shifts))
+            if nbytes == 0:
+                raise AmError(AM_EINVAL, am_last_error())
+            return am_price_rqmc_batch(params, n_paths, n_dates, basis, dtype, shifts, self.workspace(nbytes),
+                                       self.stream)
         nbytes = am_workspace_bytes(n_paths, n_dates, basis, dtype)
-        ws = self.workspace(nbytes)
-        return am_price_american_rqmc(params, n_paths, n_dates, basis, dtype, shifts, ws, self.stream)
+        return am_price_american_rqmc(params, n_paths, n_dates, basis, dtype, shifts, self.workspace(nbytes),
+                                      self.stream)
 
     def price_batch(self, opts, basis: am_basis, dtype, wait: bool = True):
         nbytes = am_batch_workspace_bytes(opts, basis, dtype)

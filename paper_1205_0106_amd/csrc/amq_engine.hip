@@ -668,14 +668,18 @@ int am_price_american_noalloc(const am_params *params, int64_t n_paths, int32_t 
     return AM_OK;
 }
 
-int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
-                           int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
-                           size_t ws_bytes, void *hip_stream, double *h_out)
+}  // extern "C"
+
+namespace {
+
+// Randomised QMC, one replicate after another in the single-option layout
+// (the replicates' prices collected on the device; the last replicate's
+// final step aggregates them).
+int rqmc_serial(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
+                size_t ws_bytes, void *hip_stream, double *h_out)
 {
-    int rc = validate(params, n_paths, n_dates, basis, dtype);
-    if (rc) return rc;
-    if (n_rep < 1 || n_rep > amq::kMaxReps || !h_shifts)
-        return fail(AM_EINVAL, "n_rep must be in [1, %d] and shifts non-NULL", amq::kMaxReps);
+    int rc = AM_OK;
     dtype = storage_of(n_paths, dtype);
     Layout L = make_layout(n_paths, n_dates, dtype);
     if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
@@ -698,6 +702,10 @@ int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_d
     HIP_TRY(hipStreamSynchronize(stream));
     return AM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 // ---------------------------------------------------------------------------
 // Batches
@@ -907,9 +915,11 @@ namespace {
 // bounds the persistent grid (a fraction of the device when several batches
 // run side by side); cooperative selects hipLaunchCooperativeKernel.
 // staging (optional, pinned, staging_bytes) holds the uploaded tables.
+// shifts (nullable): per option, the device address of its digital shift
+// ([n_dates] words; randomised QMC); all options of the batch or none.
 int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis basis, int32_t dtype,
                   char *ws, const BatchPlan &P, hipStream_t stream, int grid_cap, bool cooperative,
-                  char *staging, size_t staging_bytes, int ppt)
+                  char *staging, size_t staging_bytes, int ppt, const uint32_t *const *shifts = nullptr)
 {
     int rc = AM_OK;
     const int fp64 = dtype == AM_FP64;
@@ -955,6 +965,7 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
         const double dt = op.params.T / (double)op.n_dates;
         d.mu = (op.params.r - 0.5 * op.params.sigma * op.params.sigma) * dt;
         d.vol = op.params.sigma * sqrt(dt);
+        d.shift = shifts ? shifts[i] : nullptr;
         for (int g = 0; g < d.G; ++g) tile_opt.push_back(i);
         tiles += d.G;
         if (d.G > max_G) max_G = d.G;
@@ -1005,7 +1016,7 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     }
     HIP_TRY(amq::launch_generate_batch((const amq::BatchOpt *)(ws + P.off_desc),
                                        (const amq::GenUnit *)(ws + P.off_units), (int)units.size(),
-                                       st->d_V, gsync, P.max_M, fp64, stream));
+                                       st->d_V, gsync, P.max_M, fp64, shifts != nullptr, stream));
     if (pr) HIP_TRY(hipEventRecord(pr->e[1], stream));
     amq::BatchGlobal g;
     memset(&g, 0, sizeof g);
@@ -1035,19 +1046,25 @@ size_t staging_bytes_for(const BatchPlan &P, int n)
 // tile of part h (0: batch_ppt's choice); grid_cap[h]: cap on part h's
 // persistent grid (0: the device's resident capacity); staging (optional,
 // pinned) holds both parts' tables, part 1's after part 0's.
+// shifts (nullable): per caller option, the device address of its digital
+// shift (see enqueue_batch).
 int enqueue_split(DevState *st, const SplitBatch &B, am_basis basis, int32_t dtype, char *ws,
                   hipStream_t stream, const int *grid_cap, bool cooperative, char *staging,
-                  size_t staging_bytes, const int *ppt_in)
+                  size_t staging_bytes, const int *ppt_in, const uint32_t *const *shifts = nullptr)
 {
     size_t so = 0;
     for (int h = 0; h < 2; ++h) {
         if (!B.n(h)) continue;
+        std::vector<const uint32_t *> part_shifts;
+        if (shifts)
+            for (int j = 0; j < B.n(h); ++j) part_shifts.push_back(shifts[B.idx[h][j]]);
         const int ppt = ppt_in && ppt_in[h] ? ppt_in[h]
                                             : batch_ppt(B.opts[h].data(), B.n(h), basis, dtype, B.storage[h]);
         const size_t need = staging_bytes_for(B.P[h], B.n(h));
         char *stg = staging && so + need <= staging_bytes ? staging + so : nullptr;
         int rc = enqueue_batch(st, B.opts[h].data(), B.n(h), basis, B.storage[h], ws + B.off[h], B.P[h], stream,
-                               grid_cap ? grid_cap[h] : 0, cooperative, stg, stg ? need : 0, ppt);
+                               grid_cap ? grid_cap[h] : 0, cooperative, stg, stg ? need : 0, ppt,
+                               shifts ? part_shifts.data() : nullptr);
         if (rc) return rc;
         so += align256(need);
     }
@@ -1129,6 +1146,104 @@ int am_price_batch(const am_option *opts, int32_t n_opts, am_basis basis, int32_
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(stream));
     return scatter_split_results(B, res.data(), h_out, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The replicates of a randomised QMC call as a batch of identical options,
+// each with its own digital shift.
+void rqmc_options(const am_params *params, int64_t n_paths, int32_t n_dates, int32_t n_rep,
+                  std::vector<am_option> &opts)
+{
+    am_option o;
+    memset(&o, 0, sizeof o);
+    o.params = *params;
+    o.n_paths = n_paths;
+    o.n_dates = n_dates;
+    opts.assign(n_rep, o);
+}
+
+int check_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype,
+               int32_t n_rep, const uint32_t *h_shifts)
+{
+    int rc = validate(params, n_paths, n_dates, basis, dtype);
+    if (rc) return rc;
+    if (n_rep < 1 || n_rep > amq::kMaxReps || !h_shifts)
+        return fail(AM_EINVAL, "n_rep must be in [1, %d] and shifts non-NULL", amq::kMaxReps);
+    return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t am_rqmc_workspace_bytes(int64_t n_paths, int32_t n_dates, am_basis basis, int32_t dtype, int32_t n_rep)
+{
+    if (n_rep < 1 || n_rep > amq::kMaxReps) return 0;
+    std::vector<am_option> opts;
+    am_params p = {100.0, 100.0, 0.0, 0.2, 1.0, 0, 1};   // sizes do not depend on the option
+    rqmc_options(&p, n_paths, n_dates, n_rep, opts);
+    if (validate_batch(opts.data(), n_rep, basis, dtype)) return 0;
+    SplitBatch B;
+    split_batch(opts.data(), n_rep, dtype, B);
+    return B.total + align256((size_t)n_rep * n_dates * 4);
+}
+
+int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                           int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
+                           size_t ws_bytes, void *hip_stream, double *h_out)
+{
+    int rc = check_rqmc(params, n_paths, n_dates, basis, dtype, n_rep, h_shifts);
+    if (rc) return rc;
+    return rqmc_serial(params, n_paths, n_dates, basis, dtype, n_rep, h_shifts, d_workspace, ws_bytes,
+                       hip_stream, h_out);
+}
+
+int am_price_rqmc_batch(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
+                        int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
+                        size_t ws_bytes, void *hip_stream, double *h_out)
+{
+    int rc = check_rqmc(params, n_paths, n_dates, basis, dtype, n_rep, h_shifts);
+    if (rc) return rc;
+    if (!h_out) return fail(AM_EINVAL, "h_out is required (the mean is formed on the host)");
+    const size_t need = am_rqmc_workspace_bytes(n_paths, n_dates, basis, dtype, n_rep);
+    if (!d_workspace || ws_bytes < need || ((uintptr_t)d_workspace & 255u))
+        return fail(AM_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned", need);
+    // every replicate at once: one generation launch and one persistent sweep
+    std::vector<am_option> opts;
+    rqmc_options(params, n_paths, n_dates, n_rep, opts);
+    SplitBatch B;
+    split_batch(opts.data(), n_rep, dtype, B);
+    DevState *st = nullptr;
+    rc = get_state(&st);
+    if (rc) return rc;
+    char *ws = (char *)d_workspace;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const uint32_t *d_sh = (const uint32_t *)(ws + B.total);
+    std::vector<const uint32_t *> shifts(n_rep);
+    for (int r = 0; r < n_rep; ++r) shifts[r] = d_sh + (size_t)r * n_dates;
+    HIP_TRY(hipMemcpyAsync(ws + B.total, h_shifts, (size_t)n_rep * n_dates * 4, hipMemcpyHostToDevice, stream));
+    rc = enqueue_split(st, B, basis, dtype, ws, stream, nullptr, true, nullptr, 0, nullptr, shifts.data());
+    if (rc) return rc;
+    std::vector<double> res(split_results_doubles(B)), pr(2 * (size_t)n_rep);
+    rc = enqueue_split_results(B, ws, res.data(), stream);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(stream));
+    rc = scatter_split_results(B, res.data(), pr.data(), nullptr);
+    if (rc) return rc;
+    // mean and replicate standard error, in the order and arithmetic of the
+    // one-after-another form's final step
+    double s1r = 0.0;
+    for (int q = 0; q < n_rep; ++q) s1r += pr[2 * q];
+    const double m = s1r / (double)n_rep;
+    double s2r = 0.0;
+    for (int q = 0; q < n_rep; ++q) s2r += (pr[2 * q] - m) * (pr[2 * q] - m);
+    h_out[0] = m;
+    h_out[1] = n_rep > 1 ? sqrt(s2r / (double)(n_rep - 1) / (double)n_rep) : 0.0;
+    for (int q = 0; q < n_rep; ++q) h_out[2 + q] = pr[2 * q];
+    return AM_OK;
 }
 
 void am_debug_set_batch_ppt(int32_t ppt) { g_batch_ppt = ppt; }

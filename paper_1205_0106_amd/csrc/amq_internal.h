@@ -134,6 +134,7 @@ struct alignas(64) BatchOpt {
     int32_t tile_base;        // first partial slot / global tile index
     int32_t is_call, allow_exercise, pad;
     double S0, K, r, sigma, T, mu, vol;
+    const uint32_t *shift;    // [M] digital shift per dimension (randomised QMC), or null
 };
 
 struct GenUnit {              // one generation workgroup: blocks [b0, b1) of option opt
@@ -162,7 +163,7 @@ __host__ __device__ size_t generate_lds_bytes(int M, int fp64);
 hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
-                                 hipStream_t s);
+                                 bool shifted, hipStream_t s);
 hipError_t launch_sweep_batch(const BatchOpt *opts, const int32_t *tile_opt, const BatchGlobal &g,
                               int grid, int fp64, int ppt, int degree, bool cooperative, hipStream_t s);
 int sweep_batch_blocks_per_cu(int fp64, int laguerre, int ppt, int degree);

@@ -741,7 +741,7 @@ __device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t
     return a;
 }
 
-template <typename T>
+template <typename T, bool MID>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ units,
                  const uint32_t *__restrict__ V, uint32_t *gsync)
@@ -769,16 +769,23 @@ gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ 
         n.wl = b.wl; n.wr = b.wr; n.sd = b.sd;
         nodes[q] = n;
     }
-    gen_body<T, 0, false, LdsNode>(a, V, nodes, nullptr, u.b0 == 0, w0, w1);
+    gen_body<T, 0, MID, LdsNode>(a, V, nodes, MID ? o.shift : nullptr, u.b0 == 0, w0, w1);
 }
 
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
-                                 hipStream_t s)
+                                 bool shifted, hipStream_t s)
 {
     const size_t lds = (generate_lds_bytes(max_dates, fp64) + 15) / 16 * 16 + (size_t)max_dates * sizeof(LdsNode);
-    if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
-    else      hipLaunchKernelGGL((gen_batch_kernel<float>), dim3(n_units), dim3(kWG), lds, s, opts, units, V, gsync);
+    const dim3 g(n_units), b(kWG);
+    if (shifted) {
+        // randomised QMC: every option of the batch carries its digital shift
+        if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double, true>), g, b, lds, s, opts, units, V, gsync);
+        else      hipLaunchKernelGGL((gen_batch_kernel<float, true>), g, b, lds, s, opts, units, V, gsync);
+    } else {
+        if (fp64) hipLaunchKernelGGL((gen_batch_kernel<double, false>), g, b, lds, s, opts, units, V, gsync);
+        else      hipLaunchKernelGGL((gen_batch_kernel<float, false>), g, b, lds, s, opts, units, V, gsync);
+    }
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ int sweep_blocks_per_cu(int, int, int, int, int) { return 1; }
 __host__ __device__ size_t generate_lds_bytes(int M, int) { return (size_t)M * 64; }
 hipError_t launch_paper(const PaperArgs &, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_generate_batch(const BatchOpt *, const GenUnit *, int, const uint32_t *, uint32_t *, int, int,
-                                 hipStream_t)
+                                 bool, hipStream_t)
 {
     return hipErrorNotSupported;
 }
@@ -153,6 +153,10 @@ static void batch_sizes()
     const size_t w64 = am_batch_workspace_bytes(o.data(), (int32_t)o.size(), b, AM_FP64);
     CHECK(w32 > 0 && w64 > w32);
     CHECK(am_batch_workspace_bytes(o.data(), 0, b, AM_FP64) == 0);
+    CHECK(am_rqmc_workspace_bytes(4096, 20, b, AM_FP64, 0) == 0);
+    CHECK(am_rqmc_workspace_bytes(4096, 20, b, AM_FP64, 65) == 0);
+    CHECK(am_rqmc_workspace_bytes(4096, 20, b, AM_FP64, 8) > am_rqmc_workspace_bytes(4096, 20, b, AM_FP64, 2));
+    CHECK(am_rqmc_workspace_bytes(1 << 15, 20, b, AM_FP32_BULK, 8) < am_rqmc_workspace_bytes(1 << 15, 20, b, AM_FP64, 8));
     o[5].n_dates = 0;
     CHECK(am_batch_workspace_bytes(o.data(), (int32_t)o.size(), b, AM_FP64) == 0);
 }

@@ -511,3 +511,30 @@ def test_rqmc_matches_oracle(amq, orc, pricer, dtype):
     assert np.abs(reps - oreps).max() <= TOL[dtype]
     assert abs(mean - omean) <= TOL[dtype]
     assert abs(se - ose) <= 0.05 * ose + TOL[dtype] / 10
+
+
+@pytest.mark.parametrize("dtype,N,R", [("fp64", 1 << 12, 8), ("fp32", 1 << 15, 5), ("fp64", 3000, 1),
+                                       ("fp32", 20000, 16)])
+def test_rqmc_fused_equals_serial_and_oracle(amq, orc, pricer, dtype, N, R):
+    # all replicates at once (a batch of shifted options) against one after
+    # another: the same replicate prices to rounding, both against the oracle
+    # on the same storage
+    w = CONFIG1
+    M = 20
+    rng = np.random.default_rng(0x5EED + R)
+    sh = rng.integers(0, 2 ** 32, size=(R, M), dtype=np.uint64).astype(np.uint32)
+    p = amq.make_params(**w.params())
+    b = amq.make_basis(*w.basis)
+    log(f"  rqmc fused vs serial {dtype} N={N} R={R}")
+    fm, fse, freps = pricer.price_rqmc(p, N, M, b, dtype, sh, fused=True)
+    sm, sse, sreps = pricer.price_rqmc(p, N, M, b, dtype, sh, fused=False)
+    omean, ose, oreps = orc.price_american_rqmc(**w.params(), N=N, M=M, shifts=sh, kind=orc.MONOMIAL,
+                                                degree=2, store32=stores32(dtype, N))
+    log(f"    fused {fm:.10f} serial {sm:.10f} oracle {omean:.10f}")
+    assert np.abs(freps - sreps).max() <= 1e-9
+    assert np.abs(freps - oreps).max() <= TOL[dtype]
+    assert abs(fm - omean) <= TOL[dtype]
+    if R > 1:
+        assert abs(fse - sse) <= 1e-9 and abs(fse - ose) <= 0.05 * ose + TOL[dtype] / 10
+    else:
+        assert fse == 0.0 and sse == 0.0
