@@ -889,6 +889,24 @@ __device__ __forceinline__ Vec<float> read_slot(const Vec<float> *base, uint32_t
     return v;
 }
 
+// Two 16-byte LDS reads under one wait (the second read's latency overlaps
+// the first's), complete on return.
+__device__ __forceinline__ void read_slot2(const Vec<float> *base0, const Vec<float> *base1, uint32_t lane_off,
+                                           Vec<float> &v0, Vec<float> &v1)
+{
+    using V4 = float __attribute__((ext_vector_type(4)));
+    const uint32_t b0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base0;
+    const uint32_t b1 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base1;
+    V4 r0, r1;
+    uint32_t t0, t1;
+    asm volatile("v_add_u32 %2, %4, %6\n\tv_add_u32 %3, %5, %6\n\tds_read_b128 %0, %2\n\t"
+                 "ds_read_b128 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(r0), "=&v"(r1), "=&v"(t0), "=&v"(t1)
+                 : "s"(b0), "s"(b1), "v"(lane_off));
+    v0.v[0] = r0.x; v0.v[1] = r0.y; v0.v[2] = r0.z; v0.v[3] = r0.w;
+    v1.v[0] = r1.x; v1.v[1] = r1.y; v1.v[2] = r1.z; v1.v[3] = r1.w;
+}
+
 // Slab-resident tile: per date, a moment pass over the slab, the
 // device-wide sum and solve, then the exercise update over the same values.
 // A thread's 4-path vectors ("slots", j = 0..NVEC-1) are processed in the
@@ -1045,11 +1063,20 @@ __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *
         const double dsg = dk * sg, dnsk = dk * nsk;
         // the next date's slab (the last date requests date 1 again, unused)
         const float *nrow = S + (size_t)(k >= 2 ? k - 2 : 0) * ld;
+        // LDS slots in pairs: the even slot's read also fetches the next one
+        Vec<float> pend;
         static_for<0, NVEC>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
             // the re-read slots again, PF ahead
             if constexpr (t + PF >= NKL + NKR && t + PF < NVEC) request(row, Ic<t + PF>{});
-            const Vec<float> v = slot(tc, false);
+            Vec<float> v;
+            if constexpr (t < NKL && t % 2 == 0 && t + 1 < NKL) {
+                read_slot2(resident_slot<t, NKL>(), resident_slot<t + 1, NKL>(), lane_off, v, pend);
+            } else if constexpr (t < NKL && t % 2 == 1) {
+                v = pend;
+            } else {
+                v = slot(tc, false);
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 pv[t * 4 + e] = resident_update<CALL, D>(v.v[e], pv[t * 4 + e], kthr_u, xa, xb, dsg, dnsk, gam);
