@@ -111,6 +111,8 @@ def parse():
                     help="the paper's Table 2 shape: ten exercise points, 10 .. 10^6 paths, GPU and oracle")
     ap.add_argument("--serve", type=float, default=0.0, metavar="SECONDS",
                     help="serving mode: replay Poisson arrivals (200 req/s) for SECONDS")
+    ap.add_argument("--serve-rate", type=float, default=200.0, metavar="REQ_PER_S",
+                    help="arrival rate of the serving replay (--serve)")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="batch mode: price N options of the seeded batch workload in one call")
     ap.add_argument("--paper-estimator", action="store_true",
@@ -163,14 +165,15 @@ def time_steps(amq, pricer, p, b, w, dtype, steps, warmup):
                 price=float(res[0]), std_err=float(res[1]))
 
 
-def serve(seconds, dtype):
-    """Open-loop replay of seeded Poisson arrivals (200 req/s); each request is
-    one option drawn as in the batch workload with 2^12-2^20 paths and 12-365
-    dates; latency = completion - scheduled arrival (no coordinated omission)."""
+def serve(seconds, dtype, rate=200.0):
+    """Open-loop replay of seeded Poisson arrivals (`rate` req/s); each request
+    is one option drawn as in the batch workload with 2^12-2^20 paths and
+    12-365 dates; latency = completion - scheduled arrival (no coordinated
+    omission)."""
     import numpy as np
     import paper_1205_0106_amd as amq
     from paper_1205_0106_amd.workloads import batch_options, poisson_arrivals
-    arr = poisson_arrivals(200.0, seconds)
+    arr = poisson_arrivals(rate, seconds)
     specs = batch_options(len(arr), seed=0x12050107, log2_paths=(12.0, 20.0), dates=(12, 365))
     opts = amq.make_options(specs)
     b = amq.make_basis("monomial", 2)
@@ -207,7 +210,7 @@ def serve(seconds, dtype):
         "value": steps / (t_end - t0), "unit": "path-steps/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f64", "storage": "f32" if dtype == "fp32" else "f64",
         "data": "synthetic (seeded Poisson arrivals and option mix)",
-        "config": {"workload": f"serving: Poisson 200 req/s for {seconds:g} s, paths 2^12-2^20, "
+        "config": {"workload": f"serving: Poisson {rate:g} req/s for {seconds:g} s, paths 2^12-2^20, "
                                "dates 12-365, HBM admission budget 64 GB", "requests": len(arr),
                    "basis": "monomial degree 2"},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -451,7 +454,7 @@ def main():
         copy_calibration(args.copy_calibration, args.steps)
         return
     if args.serve:
-        print(json.dumps(serve(args.serve, args.dtype or "fp32")), flush=True)
+        print(json.dumps(serve(args.serve, args.dtype or "fp32", args.serve_rate)), flush=True)
         return
     if args.batch:
         print(json.dumps(batch_run(args.batch, args.dtype or "fp32", args.steps, args.warmup)), flush=True)
@@ -555,6 +558,12 @@ def main():
                                                  "batches", "offered_path_steps_per_s")}
             out["serving"]["workload"] = sv["config"]["workload"]
             out["serving"]["requests"] = sv["config"]["requests"]
+            # the same mix at ten times the rate for a shorter window: the
+            # dispatcher merges waiting requests into batches under load
+            hv = serve(max(2.0, args.serve_seconds / 3), "fp32", rate=2000.0)
+            out["serving_2000rps"] = {k: hv[k] for k in ("value", "unit", "p50_ms", "p99_ms", "mean_ms",
+                                                         "completed_ok", "batches", "offered_path_steps_per_s")}
+            out["serving_2000rps"]["requests"] = hv["config"]["requests"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     out["gpu"] = torch.cuda.get_device_name(0)

@@ -133,3 +133,26 @@ def test_serving_request_larger_than_a_stream_share(amq, dtype):
     finally:
         amq.am_debug_set_batch_ppt(0)
 
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_serving_burst_is_merged(amq, dtype):
+    # a burst of requests arriving together: the dispatcher merges waiting
+    # requests into batches (far fewer batches than requests), and every
+    # result is still the request's result alone (batch tiles are per option)
+    lo = 12.0 if dtype == "fp64" else 14.0
+    specs = batch_options(64, seed=41, log2_paths=(lo, 15.0), dates=(12, 40))
+    b = amq.make_basis("monomial", 2)
+    opts = amq.make_options(specs)
+    with amq.Server(1 << 30, b, dtype, n_streams=2, max_batch_requests=32) as srv:
+        for i in range(len(specs)):
+            srv.submit(opts[i], i)
+        got = _collect(srv, len(specs))
+        st = srv.stats()
+    log(f"  {dtype}: {st['batches']:.0f} batches for {st['requests']:.0f} requests")
+    assert st["requests"] == len(specs) and st["batches"] <= len(specs) // 4
+    for i in range(0, 64, 9):
+        with amq.Server(1 << 30, b, dtype, n_streams=1, max_batch_requests=1) as one:
+            one.submit(opts[i], 0)
+            alone = _collect(one, 1)[0]
+        assert got[i]["status"] == 0 and got[i]["price"] == alone["price"], (i, got[i], alone)
