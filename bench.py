@@ -510,7 +510,7 @@ def main():
         # arithmetic of the path: FP32 bulk computes in binary64 and stores
         # path values and cashflows in binary32 (each rounded once); FP64 is
         # binary64 throughout
-        "dtype": "f32+f64" if dtype == "fp32" else "f64",
+        "dtype": "f64",
         "data": "synthetic (on-device Sobol paths)",
         "config": {"workload": w.name, "n_paths": w.n_paths, "n_dates": w.n_dates,
                    "basis": f"{w.basis[0]} degree {w.basis[1]}",
