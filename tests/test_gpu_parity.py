@@ -261,6 +261,28 @@ def test_ragged_sizes(amq, orc, pricer, N, M, dtype):
     assert abs(price - ores.price) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("M", [365, "max"])
+def test_many_dates_up_to_the_maximum(amq, orc, pricer, dtype, M):
+    # the serving workload's longest schedules and the engine's date limit:
+    # bridge depth, Sobol dimensions and on-chip lane tables at their largest
+    M = amq.am_max_dates() if M == "max" else M
+    N = 20000
+    kw = dict(S0=100.0, K=100.0, r=0.04, sigma=0.3, T=2.0)
+    price, se, v = gpu_price(amq, pricer, None, N=N, M=M, dtype=dtype, basis=("monomial", 2), **kw)
+    ores, od = oracle_price(orc, None, N=N, M=M, basis=("monomial", 2), dtype=dtype, **kw)
+    log(f"  M={M} {dtype}: gpu {price:.10f} oracle {ores.price:.10f}")
+    assert abs(price - ores.price) <= TOL[dtype]
+    nitm = v["rec"].cpu().numpy()[1:M, 9].astype(np.int64)
+    assert np.abs(nitm - od["nitm"][1:M]).max() <= (0 if dtype == "fp64" else 1)
+    want = orc.paths_range(**kw, first=N - 100, count=100, M=M)
+    got = v["S"][:, N - 100:N].cpu().numpy()
+    if dtype == "fp32":
+        check_stored32(got, want, f"last paths at M={M}")
+    else:
+        assert np.abs(got - want).max() / want.max() <= 1e-12
+
+
 @pytest.mark.parametrize("N,M", [(4, 3), (1000, 17), (4097, 12), (16383, 5)])
 def test_fp32_below_path_floor_is_the_fp64_result(amq, pricer, N, M):
     # the storage rule: such an FP32-bulk request is the FP64 request, bitwise
