@@ -68,6 +68,14 @@ int fail(int code, const char *fmt, ...)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Generation waves launched per CU (each wave takes an equal range of 64-path
+// blocks): many short ranges leave no long tail of waves on a few CUs.  With
+// 16 waves resident per CU, measured on config 4 (2^24 paths x 252 dates):
+// 32 per CU 11.6 ms, 128 10.8-11.0, 256 10.7-10.8, 512 10.8, 1024 10.9; the
+// batch of 1024 options: 32 39.9 ms, 256 35.6-36.2, 512 35.1, 1024 35.0.
+constexpr int64_t kGenWavesPerCU = 256;
+constexpr int64_t kBatchGenWavesPerCU = 512;
+
 // Storage a pricing request gets: binary32 bulk storage only from
 // AM_FP32_MIN_PATHS paths up (below that one decision that rounds the other
 // way can exceed the FP32-bulk tolerance by itself).
@@ -391,7 +399,7 @@ int enqueue(DevState *st, const am_params *p, int64_t N, int32_t M, am_basis b, 
     ga.N = N; ga.ld = L.ld;
     ga.nblocks = L.ld / 64;
     ga.M = M;
-    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    const int64_t target_waves = (int64_t)st->num_cu * kGenWavesPerCU;
     int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
     ga.R = (int32_t)(R < 1 ? 1 : R);
     ga.what = 0;
@@ -876,7 +884,7 @@ int am_price_paper_estimator(const am_params *params, int64_t n_paths, int32_t n
     ga.datec = (amq::DateConst *)(ws + L.off_datec);
     ga.sync = (uint32_t *)(ws + L.off_result + 64);
     ga.N = n_paths; ga.ld = L.ld; ga.nblocks = L.ld / 64; ga.M = n_points;
-    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    const int64_t target_waves = (int64_t)st->num_cu * kGenWavesPerCU;
     int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
     ga.R = (int32_t)(R < 1 ? 1 : R);
     ga.what = 0;
@@ -973,10 +981,11 @@ int enqueue_batch(DevState *st, const am_option *opts, int32_t n_opts, am_basis 
     const int grid = tiles < capacity ? tiles : capacity;
     if (max_G > grid)
         return fail(AM_EDIM, "an option needs %d tiles but only %d workgroups are resident", max_G, grid);
-    // generation units: about 32 waves per CU in total, each wave given about
-    // the same number of path-steps (blocks x dates), so options with many
-    // dates get fewer blocks per wave and no unit outlasts the rest
-    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    // generation units: about kBatchGenWavesPerCU waves per CU in total, each
+    // wave given about the same number of path-steps (blocks x dates), so
+    // options with many dates get fewer blocks per wave and no unit outlasts
+    // the rest
+    const int64_t target_waves = (int64_t)st->num_cu * kBatchGenWavesPerCU;
     int64_t total_work = 0;
     for (int i = 0; i < n_opts; ++i) total_work += (P.ld[i] / 64) * (int64_t)opts[i].n_dates;
     const int64_t wave_work = (total_work + target_waves - 1) / target_waves;
@@ -1931,7 +1940,7 @@ int am_debug_generate(int32_t what, const am_params *params, int64_t n_paths, in
     ga.datec = (amq::DateConst *)(d + align256(out_b));
     ga.sync = (uint32_t *)(d + align256(out_b) + align256((size_t)(n_dims + 1) * sizeof(amq::DateConst)));
     ga.N = n_paths; ga.ld = ld; ga.nblocks = (n_paths + 63) / 64; ga.M = n_dims;
-    const int64_t target_waves = (int64_t)st->num_cu * 32;
+    const int64_t target_waves = (int64_t)st->num_cu * kGenWavesPerCU;
     int64_t R = (ga.nblocks + target_waves - 1) / target_waves;
     ga.R = (int32_t)(R < 1 ? 1 : R);
     ga.what = what;
