@@ -294,8 +294,8 @@ int am_debug_schedule(int32_t n_dates, int32_t *m, int32_t *dim, int32_t *left,
 int am_profile_enable(int32_t on);
 int am_profile_read(double ms[2], int64_t *calls);
 
-/* Time the batch with each candidate tile shape (paths per thread: FP32 4
- * and 16, FP64 2 and 8; two timed runs each after a warm-up), remember the
+/* Time the batch with each candidate tile shape (paths per thread: FP32 16
+ * and 64, FP64 8 and 32; two timed runs each after a warm-up), remember the
  * faster one for this shape class (precision, degree, batch size and total
  * path-steps rounded to powers of two) for later am_price_batch calls in the
  * process, and return it in *best_ppt (ms_out: mean milliseconds per
@@ -351,7 +351,7 @@ typedef struct am_result {
  * wait behind it).  Paths and cashflows stay resident in the pool until a
  * request completes.  Results are those of am_price_batch, hence identical
  * to pricing the request alone.  The batch tile is the default one (FP32
- * bulk 16 paths per thread, FP64 8), whatever am_batch_autotune chose. */
+ * bulk 64 paths per thread, FP64 32), whatever am_batch_autotune chose. */
 int am_server_create(const am_server_config *cfg, am_server **out);
 
 /* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now.
@@ -384,8 +384,8 @@ int am_server_destroy(am_server *server);
  * attached to it) to tear down after its own finalisation. */
 int am_shutdown(void);
 
-/* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 4
- * or 16, FP64: 2 or 8; 0 restores the default).  Results of one option are
+/* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 16
+ * or 64, FP64: 8 or 32; 0 restores the default: the larger).  Results of one option are
  * identical for a given choice; different choices change the reduction
  * order (differences at rounding level). */
 void am_debug_set_batch_ppt(int32_t ppt);

@@ -1329,8 +1329,8 @@ inline const void *sweep_entry(int degree)
 }
 
 // Paths per thread built.  binary32: 4, 16, 64, 128 (256-thread groups),
-// 4, 8, 64, 128 (512-thread groups), batch 4, 16.  binary64: 2, 8, 16, 64 (256), 2, 4,
-// 8 (512), batch 2, 8.
+// 4, 8, 64, 128 (512-thread groups), batch 16, 64.  binary64: 2, 8, 16, 64 (256), 2, 4,
+// 8 (512), batch 8, 32.
 template <typename T, bool LAG>
 inline const void *sweep_table(int ppt, int degree, int kind)
 {
@@ -1338,8 +1338,8 @@ inline const void *sweep_table(int ppt, int degree, int kind)
         if (kind == 3) return nullptr;   // no slab-resident binary64 tiles
         if (kind == 1) {
             switch (ppt) {
-            case 2: return sweep_entry<T, 2, LAG, 1>(degree);
             case 8: return sweep_entry<T, 8, LAG, 1>(degree);
+            case 32: return sweep_entry<T, 32, LAG, 1>(degree);
             default: return nullptr;
             }
         }
@@ -1361,8 +1361,8 @@ inline const void *sweep_table(int ppt, int degree, int kind)
     } else {
         if (kind == 1) {
             switch (ppt) {
-            case 4: return sweep_entry<T, 4, LAG, 1>(degree);
             case 16: return sweep_entry<T, 16, LAG, 1>(degree);
+            case 64: return sweep_entry<T, 64, LAG, 1>(degree);
             default: return nullptr;
             }
         }

@@ -88,7 +88,7 @@ def test_batch_deterministic_and_tile_choice(amq, pricer):
     b = amq.make_basis("monomial", 3)
     a = pricer.price_batch(opts, b, "fp32")
     assert np.array_equal(a, pricer.price_batch(opts, b, "fp32"))
-    amq.am_debug_set_batch_ppt(4)
+    amq.am_debug_set_batch_ppt(16)
     try:
         c = pricer.price_batch(opts, b, "fp32")
     finally:
@@ -118,14 +118,14 @@ def test_batch_autotune_and_graph_replay(amq, orc, pricer):
     ws = pricer.workspace(amq.am_batch_workspace_bytes(opts, b, "fp32"))
     best, ms = amq.am_batch_autotune(opts, b, "fp32", ws, pricer.stream)
     log(f"  autotune: best ppt {best}, ms {ms}")
-    assert best in (4, 16) and all(m > 0 for m in ms)
+    assert best in (16, 64) and all(m > 0 for m in ms)
     tuned = pricer.price_batch(opts, b, "fp32")
     # each tile shape is an FP32 result within tolerance of the oracle
     for i, d in enumerate(specs):
         want = _want(amq, orc, d, "fp32")
         assert abs(ref[i, 0] - want.price) <= TOL["fp32"], (i, ref[i, 0], want.price)
         assert abs(tuned[i, 0] - want.price) <= TOL["fp32"], (i, tuned[i, 0], want.price)
-    amq.am_debug_set_batch_ppt(16)
+    amq.am_debug_set_batch_ppt(64)
     try:
         g = amq.BatchGraph(opts, b, "fp32", ws)
         eager = pricer.price_batch(opts, b, "fp32")

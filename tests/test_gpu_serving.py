@@ -124,7 +124,7 @@ def test_serving_request_larger_than_a_stream_share(amq, dtype):
             srv.submit(opts[i], i)
         got = _collect(srv, len(specs))
     pr = amq.Pricer(0)
-    amq.am_debug_set_batch_ppt(16 if dtype == "fp32" else 8)
+    amq.am_debug_set_batch_ppt(64 if dtype == "fp32" else 32)
     try:
         for i, d in enumerate(specs):
             assert got[i]["status"] == 0, (i, got[i])
