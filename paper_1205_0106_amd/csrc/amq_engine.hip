@@ -803,11 +803,28 @@ bool valid_batch_ppt(int32_t storage, int ppt)
 // thread, 20.6 at 32, 19.0 at 64; binary64: 56.5 at 8, 34.1 at 16, 28.3 at
 // 32).
 int default_batch_ppt(int32_t storage) { return storage == AM_FP64 ? 32 : 64; }
+int small_batch_ppt(int32_t storage) { return storage == AM_FP64 ? 8 : 16; }
+
+// The tile for a batch whose options are all the caller's (the replicates of
+// one randomised-QMC price): the larger one while the batch still yields a
+// tile per compute unit at that size, else the smaller one, so that few
+// paths still spread over the device (8 replicates of 2^17 paths in
+// binary32: 64 tiles at 64 paths per thread, 2.14 ms; 256 tiles at 16,
+// 1.46 ms).
+int shaped_batch_ppt(const am_option *opts, int32_t n, int32_t storage, int num_cu)
+{
+    const int64_t tile = (int64_t)amq::kWG * default_batch_ppt(storage);
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += (opts[i].n_paths + tile - 1) / tile;
+    return tiles >= num_cu ? default_batch_ppt(storage) : small_batch_ppt(storage);
+}
 
 // Paths per thread of the sub-batch stored as `storage` in a batch the caller
 // priced as `dtype`: the tuning hook if it names a tile of this storage
 // type, else the tile am_batch_autotune found for the batch's shape class
-// (it tunes the caller's storage type), else the default.
+// (it tunes the caller's storage type), else the default.  The default does
+// not depend on the rest of the batch, so an option prices the same alone
+// and in any mix.
 int batch_ppt(const am_option *opts, int32_t n, am_basis basis, int32_t dtype, int32_t storage)
 {
     if (g_batch_ppt && valid_batch_ppt(storage, g_batch_ppt)) return g_batch_ppt;
@@ -1239,7 +1256,11 @@ int am_price_rqmc_batch(const am_params *params, int64_t n_paths, int32_t n_date
     std::vector<const uint32_t *> shifts(n_rep);
     for (int r = 0; r < n_rep; ++r) shifts[r] = d_sh + (size_t)r * n_dates;
     HIP_TRY(hipMemcpyAsync(ws + B.total, h_shifts, (size_t)n_rep * n_dates * 4, hipMemcpyHostToDevice, stream));
-    rc = enqueue_split(st, B, basis, dtype, ws, stream, nullptr, true, nullptr, 0, nullptr, shifts.data());
+    int ppt[2] = {0, 0};
+    for (int h = 0; h < 2; ++h)
+        if (B.n(h) && !(g_batch_ppt && valid_batch_ppt(B.storage[h], g_batch_ppt)))
+            ppt[h] = shaped_batch_ppt(B.opts[h].data(), B.n(h), B.storage[h], st->num_cu);
+    rc = enqueue_split(st, B, basis, dtype, ws, stream, nullptr, true, nullptr, 0, ppt, shifts.data());
     if (rc) return rc;
     std::vector<double> res(split_results_doubles(B)), pr(2 * (size_t)n_rep);
     rc = enqueue_split_results(B, ws, res.data(), stream);
