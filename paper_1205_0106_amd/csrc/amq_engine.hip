@@ -277,39 +277,60 @@ thread_local int32_t g_tile_wg = 0, g_tile_ppt = 0;   // a forced single-option 
 
 // Tile choice for one sweep.  Every date costs one device-wide sum, whose
 // latency grows with the group count G (every group reads every group's
-// row: measured on gfx950 about 4.5 us + 13 ns per group), plus the per-date
-// work, spread over min(G, CUs) compute units.  Among the tiles whose grid is
-// co-resident, take the one with the least modelled time per date.
+// row), plus the per-date work.  Two regimes, both fitted to sweeps timed on
+// gfx950 over 2^12 .. 2^20 paths, both storage types and three bases:
+//  - small tiles (512 threads, at most 8 paths per thread) while their grid
+//    is co-resident: the exchange costs about 3.7 us + 5 ns per group and a
+//    group's pass about 12.5 ns per moment sum per path of a thread (each
+//    group has a CU to itself, so the pass's length follows the paths per
+//    thread, not the total).  They beat every 256-thread tile of the same
+//    size (two waves per SIMD hide the pass's latency) by 5-14 % below 2^16
+//    paths and up to 13 % at 2^18 - 2^19;
+//  - larger N: the work spread over min(G, CUs) compute units at ~40 lane
+//    operations per path (binary64: ~2x), against 4.5 us + 13 ns per group.
+// Among the tiles whose grid is co-resident, the least modelled time per
+// date, small tiles first.
 int choose_plan(DevState *st, int64_t N, int fp64, int laguerre, int degree, Plan *p)
 {
     const TileShape *tiles = fp64 ? kTiles64 : kTiles32;
     const int n_tiles = fp64 ? kNTiles64 : kNTiles32;
-    double best = 0.0;
-    bool found = false;
-    for (int i = 0; i < n_tiles; ++i) {
-        const int wg = tiles[i].wg, ppt = tiles[i].ppt;
-        if (wg != amq::kWG && !g_sweep_wide) continue;
-        if (g_tile_wg && (wg != g_tile_wg || ppt != g_tile_ppt)) continue;
-        const int per_cu = groups_per_cu(st, fp64, laguerre, wg, ppt, degree);
-        if (per_cu <= 0) continue;
-        int64_t gmax = (int64_t)per_cu * st->num_cu;
-        if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
-        const int64_t tile = (int64_t)wg * ppt;
-        // the tiles must cover whole padded rows (a tile reads every path it
-        // covers): tiles larger than the row padding only where they divide
-        // the padded row length
-        const int64_t ld = (N + amq::kLdAlign - 1) / amq::kLdAlign * amq::kLdAlign;
-        if (ld % tile != 0) continue;
-        const int64_t G = (N + tile - 1) / tile;
-        if (G > gmax) continue;
-        // per-date work: ~40 lane operations per path (binary64: ~2x) at
-        // 64 lanes x 4 SIMDs x 2.4 GHz per CU, on the CUs the grid covers
-        const double cus = (double)(G < st->num_cu ? G : st->num_cu);
-        const double work_us = (double)N * (fp64 ? 80.0 : 40.0) / (cus * 4.0 * 16.0 * 2.4e3);
-        const double t = 4.5 + 0.013 * (double)G + work_us;
-        if (!found || t < best) { best = t; p->wg = wg; p->ppt = ppt; p->G = (int)G; found = true; }
+    // moment sums per path and date (Hankel moments and right-hand side, or
+    // the Gram matrix, right-hand side and the Laguerre weight's exponential)
+    const double sums = laguerre ? (double)((degree + 1) * (degree + 2) / 2 + degree + 1 + 3) : 3.0 * degree + 2.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double best = 0.0;
+        bool found = false;
+        for (int i = 0; i < n_tiles; ++i) {
+            const int wg = tiles[i].wg, ppt = tiles[i].ppt;
+            const bool small = wg == 512 && ppt <= 8;
+            if (pass == 0 && !small) continue;
+            if (wg != amq::kWG && !g_sweep_wide) continue;
+            if (g_tile_wg && (wg != g_tile_wg || ppt != g_tile_ppt)) continue;
+            const int per_cu = groups_per_cu(st, fp64, laguerre, wg, ppt, degree);
+            if (per_cu <= 0) continue;
+            int64_t gmax = (int64_t)per_cu * st->num_cu;
+            if (gmax > amq::kMaxGroups) gmax = amq::kMaxGroups;
+            const int64_t tile = (int64_t)wg * ppt;
+            // the tiles must cover whole padded rows (a tile reads every path
+            // it covers): tiles larger than the row padding only where they
+            // divide the padded row length
+            const int64_t ld = (N + amq::kLdAlign - 1) / amq::kLdAlign * amq::kLdAlign;
+            if (ld % tile != 0) continue;
+            const int64_t G = (N + tile - 1) / tile;
+            if (G > gmax) continue;
+            double t;
+            if (pass == 0) {
+                t = 0.005 * (double)G + 0.0125 * sums * (double)ppt;
+            } else {
+                // per-date work at 64 lanes x 4 SIMDs x 2.4 GHz per CU
+                const double cus = (double)(G < st->num_cu ? G : st->num_cu);
+                const double work_us = (double)N * (fp64 ? 80.0 : 40.0) / (cus * 4.0 * 16.0 * 2.4e3);
+                t = 4.5 + 0.013 * (double)G + work_us;
+            }
+            if (!found || t < best) { best = t; p->wg = wg; p->ppt = ppt; p->G = (int)G; found = true; }
+        }
+        if (found) return AM_OK;
     }
-    if (found) return AM_OK;
     return fail(AM_EDIM, "n_paths = %lld exceeds what one resident sweep holds on this device",
                 (long long)N);
 }
