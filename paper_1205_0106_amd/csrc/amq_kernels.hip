@@ -46,155 +46,86 @@ namespace amq {
 // log(v) in binary64 for finite v > 0 (normal) by Tang's table method (P. T.
 // P. Tang, "Table-driven implementation of the logarithm function in IEEE
 // floating-point arithmetic", ACM TOMS 16(4), 1990): v = m 2^e with m in
-// [1/2, 1); F = 1/2 + j/256 + 1/512 from the top 7 fraction bits j of m, so
-// f = m - F is exact and |u| = |f / F| <= 2^-8; log v = e ln 2 + log F +
-// log1p(u), log1p by its Taylor series to degree 6 (truncation below 2e-18).
-// kLogTab[j] = {1/F, log F}, each rounded to nearest: 1/F by binary64
-// division, log F from a 50-digit decimal evaluation.  About 1 ulp for the
-// tail's arguments (results of magnitude 0.9 and more).
-__constant__ double kLogTab[128][2] = {
-    {0x1.fe01fe01fe020p+0, -0x1.60e52f45788e3p-1},
-    {0x1.fa11caa01fa12p+0, -0x1.5ced1e17c35c5p-1},
-    {0x1.f6310aca0dbb5p+0, -0x1.58fcddce004c4p-1},
-    {0x1.f25f644230ab5p+0, -0x1.55144fdbcbd62p-1},
-    {0x1.ee9c7f8458e02p+0, -0x1.513356667fc57p-1},
-    {0x1.eae807aba01ebp+0, -0x1.4d59d43fdaba2p-1},
-    {0x1.e741aa59750e4p+0, -0x1.4987ace0dabb0p-1},
-    {0x1.e3a9179dc1a73p+0, -0x1.45bcc464c893ap-1},
-    {0x1.e01e01e01e01ep+0, -0x1.41f8ff8471d61p-1},
-    {0x1.dca01dca01dcap+0, -0x1.3e3c43918f76cp-1},
-    {0x1.d92f2231e7f8ap+0, -0x1.3a86767257111p-1},
-    {0x1.d5cac807572b2p+0, -0x1.36d77e9d34fd7p-1},
-    {0x1.d272ca3fc5b1ap+0, -0x1.332f4314ad796p-1},
-    {0x1.cf26e5c44bfc6p+0, -0x1.2f8dab636337ap-1},
-    {0x1.cbe6d9601cbe7p+0, -0x1.2bf29f9841c3bp-1},
-    {0x1.c8b265afb8a42p+0, -0x1.285e0842ca384p-1},
-    {0x1.c5894d10d4986p+0, -0x1.24cfce6f80d9ap-1},
-    {0x1.c26b5392ea01cp+0, -0x1.2147dba47a394p-1},
-    {0x1.bf583ee868d8bp+0, -0x1.1dc619de06944p-1},
-    {0x1.bc4fd65883e7bp+0, -0x1.1a4a738b7a33cp-1},
-    {0x1.b951e2b18ff23p+0, -0x1.16d4d38c119fap-1},
-    {0x1.b65e2e3beee05p+0, -0x1.1365252bf0865p-1},
-    {0x1.b37484ad806cep+0, -0x1.0ffb54213a476p-1},
-    {0x1.b094b31d922a4p+0, -0x1.0c974c89431cep-1},
-    {0x1.adbe87f94905ep+0, -0x1.0938fae5d8e9bp-1},
-    {0x1.aaf1d2f87ebfdp+0, -0x1.05e04c1aa2c06p-1},
-    {0x1.a82e65130e159p+0, -0x1.028d2d6a963f4p-1},
-    {0x1.a574107688a4ap+0, -0x1.fe7f18eb03d3ep-2},
-    {0x1.a2c2a87c51ca0p+0, -0x1.f7eeae6b5761dp-2},
-    {0x1.a01a01a01a01ap+0, -0x1.f168f7fb05c52p-2},
-    {0x1.9d79f176b682dp+0, -0x1.eaedd2eac990cp-2},
-    {0x1.9ae24ea5510dap+0, -0x1.e47d1d32e677ep-2},
-    {0x1.9852f0d8ec0ffp+0, -0x1.de16b56ef90f0p-2},
-    {0x1.95cbb0be377aep+0, -0x1.d7ba7ad9e7da0p-2},
-    {0x1.934c67f9b2ce6p+0, -0x1.d1684d49f46aep-2},
-    {0x1.90d4f120190d5p+0, -0x1.cb200d2ceb643p-2},
-    {0x1.8e6527af1373fp+0, -0x1.c4e19b84723c2p-2},
-    {0x1.8bfce8062ff3ap+0, -0x1.beacd9e271ad1p-2},
-    {0x1.899c0f601899cp+0, -0x1.b881aa659bc93p-2},
-    {0x1.87427bcc092b9p+0, -0x1.b25fefb60cb2ep-2},
-    {0x1.84f00c2780614p+0, -0x1.ac478d020506fp-2},
-    {0x1.82a4a0182a4a0p+0, -0x1.a63865fabd0ecp-2},
-    {0x1.8060180601806p+0, -0x1.a0325ed14fda4p-2},
-    {0x1.7e225515a4f1dp+0, -0x1.9a355c33bd6bap-2},
-    {0x1.7beb3922e017cp+0, -0x1.9441434a03259p-2},
-    {0x1.79baa6bb6398bp+0, -0x1.8e55f9b349b83p-2},
-    {0x1.77908119ac60dp+0, -0x1.8873658327ccfp-2},
-    {0x1.756cac201756dp+0, -0x1.82996d3ef8bcbp-2},
-    {0x1.734f0c541fe8dp+0, -0x1.7cc7f7db46a0ep-2},
-    {0x1.713786d9c7c09p+0, -0x1.76feecb947175p-2},
-    {0x1.6f26016f26017p+0, -0x1.713e33a46a17cp-2},
-    {0x1.6d1a62681c861p+0, -0x1.6b85b4cffa3fdp-2},
-    {0x1.6b1490aa31a3dp+0, -0x1.65d558d4ce00bp-2},
-    {0x1.691473a88d0c0p+0, -0x1.602d08af091ecp-2},
-    {0x1.6719f3601671ap+0, -0x1.5a8cadbbedfa1p-2},
-    {0x1.6524f853b4aa3p+0, -0x1.54f431b7be1a9p-2},
-    {0x1.63356b88ac0dep+0, -0x1.4f637ebba9810p-2},
-    {0x1.614b36831ae94p+0, -0x1.49da7f3bcc41fp-2},
-    {0x1.5f66434292dfcp+0, -0x1.44591e0539f49p-2},
-    {0x1.5d867c3ece2a5p+0, -0x1.3edf463c1683ep-2},
-    {0x1.5babcc647fa91p+0, -0x1.396ce359bbf54p-2},
-    {0x1.59d61f123ccaap+0, -0x1.3401e12aecba1p-2},
-    {0x1.5805601580560p+0, -0x1.2e9e2bce12286p-2},
-    {0x1.56397ba7c52e2p+0, -0x1.2941afb186b7cp-2},
-    {0x1.54725e6bb82fep+0, -0x1.23ec5991eba49p-2},
-    {0x1.52aff56a8054bp+0, -0x1.1e9e1678899f4p-2},
-    {0x1.50f22e111c4c5p+0, -0x1.1956d3b9bc2fap-2},
-    {0x1.4f38f62dd4c9bp+0, -0x1.14167ef367783p-2},
-    {0x1.4d843bedc2c4cp+0, -0x1.0edd060b78081p-2},
-    {0x1.4bd3edda68fe1p+0, -0x1.09aa572e6c6d4p-2},
-    {0x1.4a27fad76014ap+0, -0x1.047e60cde83b8p-2},
-    {0x1.4880522014880p+0, -0x1.feb2233ea07cdp-3},
-    {0x1.46dce34596066p+0, -0x1.f474b134df229p-3},
-    {0x1.453d9e2c776cap+0, -0x1.ea4449f04aaf5p-3},
-    {0x1.43a2730abee4dp+0, -0x1.e020cc6235ab5p-3},
-    {0x1.420b5265e5951p+0, -0x1.d60a17f903515p-3},
-    {0x1.40782d10e6566p+0, -0x1.cc000c9db3c52p-3},
-    {0x1.3ee8f42a5af07p+0, -0x1.c2028ab17f9b4p-3},
-    {0x1.3d5d991aa75c6p+0, -0x1.b811730b823d2p-3},
-    {0x1.3bd60d9232955p+0, -0x1.ae2ca6f672bd4p-3},
-    {0x1.3a524387ac822p+0, -0x1.a454082e6ab05p-3},
-    {0x1.38d22d366088ep+0, -0x1.9a8778debaa38p-3},
-    {0x1.3755bd1c945eep+0, -0x1.90c6db9fcbcd9p-3},
-    {0x1.35dce5f9f2af8p+0, -0x1.871213750e994p-3},
-    {0x1.34679ace01346p+0, -0x1.7d6903caf5ad0p-3},
-    {0x1.32f5ced6a1dfap+0, -0x1.73cb9074fd14dp-3},
-    {0x1.3187758e9ebb6p+0, -0x1.6a399dabbd383p-3},
-    {0x1.301c82ac40260p+0, -0x1.60b3100b09476p-3},
-    {0x1.2eb4ea1fed14bp+0, -0x1.5737cc9018cddp-3},
-    {0x1.2d50a012d50a0p+0, -0x1.4dc7b897bc1c8p-3},
-    {0x1.2bef98e5a3711p+0, -0x1.4462b9dc9b3dcp-3},
-    {0x1.2a91c92f3c105p+0, -0x1.3b08b6757f2a9p-3},
-    {0x1.293725bb804a5p+0, -0x1.31b994d3a4f85p-3},
-    {0x1.27dfa38a1ce4dp+0, -0x1.28753bc11aba5p-3},
-    {0x1.268b37cd60127p+0, -0x1.1f3b925f25d41p-3},
-    {0x1.2539d7e9177b2p+0, -0x1.160c8024b27b1p-3},
-    {0x1.23eb79717605bp+0, -0x1.0ce7ecdccc28dp-3},
-    {0x1.22a0122a0122ap+0, -0x1.03cdc0a51ec0dp-3},
-    {0x1.21579804855e6p+0, -0x1.f57bc7d9005dbp-4},
-    {0x1.2012012012012p+0, -0x1.e3707ee30487bp-4},
-    {0x1.1ecf43c7fb84cp+0, -0x1.d179788219364p-4},
-    {0x1.1d8f5672e4abdp+0, -0x1.bf968769fca11p-4},
-    {0x1.1c522fc1ce059p+0, -0x1.adc77ee5aea8cp-4},
-    {0x1.1b17c67f2bae3p+0, -0x1.9c0c32d4d2548p-4},
-    {0x1.19e0119e0119ep+0, -0x1.8a6477a91dc29p-4},
-    {0x1.18ab083902bdbp+0, -0x1.78d02263d82d3p-4},
-    {0x1.1778a191bd684p+0, -0x1.674f089365a7ap-4},
-    {0x1.1648d50fc3201p+0, -0x1.55e10050e0384p-4},
-    {0x1.151b9a3fdd5c9p+0, -0x1.4485e03dbdfadp-4},
-    {0x1.13f0e8d344724p+0, -0x1.333d7f8183f4bp-4},
-    {0x1.12c8b89edc0acp+0, -0x1.2207b5c78549ep-4},
-    {0x1.11a3019a74826p+0, -0x1.10e45b3cae831p-4},
-    {0x1.107fbbe011080p+0, -0x1.ffa6911ab9301p-5},
-    {0x1.0f5edfab325a2p+0, -0x1.dda8adc67ee4ep-5},
-    {0x1.0e40655826011p+0, -0x1.bbcebfc68f420p-5},
-    {0x1.0d24456359e3ap+0, -0x1.9a187b573de7cp-5},
-    {0x1.0c0a7868b4171p+0, -0x1.788595a3577bap-5},
-    {0x1.0af2f722eecb5p+0, -0x1.5715c4c03ceefp-5},
-    {0x1.09ddba6af8360p+0, -0x1.35c8bfaa1306bp-5},
-    {0x1.08cabb37565e2p+0, -0x1.149e3e4005a8dp-5},
-    {0x1.07b9f29b8eae2p+0, -0x1.e72bf2813ce51p-6},
-    {0x1.06ab59c7912fbp+0, -0x1.a55f548c5c43fp-6},
-    {0x1.059eea0727586p+0, -0x1.63d6178690bd6p-6},
-    {0x1.04949cc1664c5p+0, -0x1.228fb1fea2e28p-6},
-    {0x1.038c6b78247fcp+0, -0x1.c317384c75f06p-7},
-    {0x1.02864fc7729e9p+0, -0x1.41929f96832f0p-7},
-    {0x1.0182436517a37p+0, -0x1.8121214586b54p-8},
-    {0x1.0080402010080p+0, -0x1.0040155d5889ep-9},
+// [1/2, 1); F = 1/2 + j/128 + 1/256 from the top 6 fraction bits j of m, so
+// f = m - F is exact and |u| = |f / F| <= 2^-7; log v = e ln 2 + log F +
+// log1p(u), log1p by its Taylor series to degree 7 (truncation below 2e-18).
+// kLogTab[j] = log F rounded to nearest from a 60-digit decimal evaluation.
+// About 1 ulp for the tail's arguments (results of magnitude 0.9 and more).
+__constant__ double kLogTab[64] = {
+    -0x1.5ee82aa241920p-1, -0x1.5707a26bb8c66p-1, -0x1.4f45a835a4e19p-1, -0x1.47a1527e8a2d3p-1,
+    -0x1.4019c2125ca93p-1, -0x1.38ae2171976e7p-1, -0x1.315da4434068bp-1, -0x1.2a2786d0ec107p-1,
+    -0x1.230b0d8bebc98p-1, -0x1.1c07849ae6007p-1, -0x1.151c3f6f29612p-1, -0x1.0e4898611cce1p-1,
+    -0x1.078bf0533c568p-1, -0x1.00e5ae5b207abp-1, -0x1.f4aa7ee03192dp-2, -0x1.e7b42c3ddad73p-2,
+    -0x1.dae75484c9616p-2, -0x1.ce42f18064743p-2, -0x1.c1c60693fa39ep-2, -0x1.b56fa04462909p-2,
+    -0x1.a93ed3c8ad9e3p-2, -0x1.9d32bea15ed3bp-2, -0x1.914a8635bf68ap-2, -0x1.85855776dcbfbp-2,
+    -0x1.79e26687cfb3ep-2, -0x1.6e60ee6af1972p-2, -0x1.630030b3aac49p-2, -0x1.57bf753c8d1fbp-2,
+    -0x1.4c9e09e172c3cp-2, -0x1.419b423d5e8c7p-2, -0x1.36b6776be1117p-2, -0x1.2bef07cdc9354p-2,
+    -0x1.214456d0eb8d4p-2, -0x1.16b5ccbacfb73p-2, -0x1.0c42d676162e3p-2, -0x1.01eae5626c691p-2,
+    -0x1.ef5ade4dcffe6p-3, -0x1.db13db0d48940p-3, -0x1.c6ffbc6f00f71p-3, -0x1.b31d8575bce3dp-3,
+    -0x1.9f6c407089664p-3, -0x1.8beafeb38fe8cp-3, -0x1.7898d85444c73p-3, -0x1.6574ebe8c133ap-3,
+    -0x1.527e5e4a1b58dp-3, -0x1.3fb45a59928ccp-3, -0x1.2d1610c86813ap-3, -0x1.1aa2b7e23f72ap-3,
+    -0x1.08598b59e3a07p-3, -0x1.ec739830a1120p-4, -0x1.c885801bc4b23p-4, -0x1.a4e7640b1bc38p-4,
+    -0x1.8197e2f40e3f0p-4, -0x1.5e95a4d9791cbp-4, -0x1.3bdf5a7d1ee64p-4, -0x1.1973bd1465567p-4,
+    -0x1.eea31c006b87cp-5, -0x1.aaef2d0fb10fcp-5, -0x1.67c94f2d4bb58p-5, -0x1.252f32f8d183fp-5,
+    -0x1.c63d2ec14aaf2p-6, -0x1.432a925980cc1p-6, -0x1.82448a388a2aap-7, -0x1.0080559588b35p-8,
 };
 
-// logF: the table's log F column, from constant memory or from an LDS copy
-// (the path generator's: its loads then wait on LDS only, not on the
-// generator's pending stores); 1/F by the reciprocal's Newton refinement.
+// exp(x) in binary64 by Tang's table method (P. T. P. Tang, "Table-driven
+// implementation of the exponential function in IEEE floating-point
+// arithmetic", ACM TOMS 15(2), 1989): n = rint(64 x / ln 2), g = x - n ln 2 / 64
+// (Cody-Waite: ln 2 / 64 split into a 53-bit head and its tail, each product
+// taken exactly inside an fma), |g| <= ln 2 / 128; exp(x) = 2^(n div 64)
+// 2^((n mod 64) / 64) e^g, with e^g - 1 by its Taylor series to degree 5
+// (truncation below 0.0055^6 / 6! < 4e-17 relative) and the table value
+// added last.  kExpTab[j] = 2^(j / 64) rounded to nearest from a 60-digit
+// decimal evaluation.  tab(j) reads the table (the path generator's LDS
+// copy).  For the log-prices the generator produces (|x| < 700).
+__constant__ double kExpTab[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+};
+
+template <typename Tab>
+__device__ __forceinline__ double exp_tab(double x, Tab tab)
+{
+    const double n = rint(x * 92.332482616893658);            // 64 / ln 2
+    const double g = fma(-n, 3.6235106466348431e-19, fma(-n, 0.010830424696249145, x));
+    double p = fma3(1.0 / 120.0, g, kInvFact4);                 // 1/4! (see exp_poly)
+    p = fma3(p, g, 1.0 / 6.0);
+    p = fma(p, g, 0.5);
+    p = fma(p, g, 1.0);
+    const int ni = (int)n;
+    const double t = tab((uint32_t)ni & 63u);
+    return ldexp(fma(t, p * g, t), ni >> 6);
+}
+
+// logF: the table, from constant memory or from an LDS copy (the path
+// generator's: its loads then wait on LDS only, not on the generator's
+// pending stores); 1/F by the reciprocal's Newton refinement.
 template <typename LogF>
 __device__ __forceinline__ double log_tab(double v, LogF logF)
 {
     const double m = __builtin_amdgcn_frexp_mant(v);
     const int e = __builtin_amdgcn_frexp_exp(v);
-    const uint32_t j = (uint32_t)((uint64_t)__double_as_longlong(m) >> 45) & 127u;
-    const double F = fma((double)j, 0x1p-8, 0.5 + 0x1p-9);
+    const uint32_t j = (uint32_t)((uint64_t)__double_as_longlong(m) >> 46) & 63u;
+    const double F = fma((double)j, 0x1p-7, 0.5 + 0x1p-8);
     const double u = (m - F) * rcp_f64(F);
-    double p = fma(u, -1.0 / 6.0, 0.2);
+    double p = fma(u, 1.0 / 7.0, -1.0 / 6.0);
+    p = fma(p, u, 0.2);
     p = fma(p, u, -0.25);
     p = fma(p, u, 1.0 / 3.0);
     p = fma(p, u, -0.5);
@@ -205,7 +136,7 @@ __device__ __forceinline__ double log_tab(double v, LogF logF)
 
 __device__ __forceinline__ double log_tab(double v)
 {
-    return log_tab(v, [](uint32_t j) { return kLogTab[j][1]; });
+    return log_tab(v, [](uint32_t j) { return kLogTab[j]; });
 }
 
 // The two branches separately: which branch a point takes, the central
@@ -249,20 +180,22 @@ template <> struct MoroParts<double> {
         const double y = ((double)x - 2147483648.0) * s;
         const double q = y < 0.0 ? (double)x * s : (4294967296.0 - (double)x) * s;
         const double t = log_tab(-log_tab(q, logF), logF);
+        // Horner steps as single fmas (three-address: the coefficients stay
+        // in registers of their own)
         double v = AMQ_C8;
-        v = v * t + AMQ_C7;
-        v = v * t + AMQ_C6;
-        v = v * t + AMQ_C5;
-        v = v * t + AMQ_C4;
-        v = v * t + AMQ_C3;
-        v = v * t + AMQ_C2;
-        v = v * t + AMQ_C1;
-        v = v * t + AMQ_C0;
+        v = fma3(v, t, AMQ_C7);
+        v = fma3(v, t, AMQ_C6);
+        v = fma3(v, t, AMQ_C5);
+        v = fma3(v, t, AMQ_C4);
+        v = fma3(v, t, AMQ_C3);
+        v = fma3(v, t, AMQ_C2);
+        v = fma3(v, t, AMQ_C1);
+        v = fma3(v, t, AMQ_C0);
         return y < 0.0 ? -v : v;
     }
     static __device__ __forceinline__ double tail_value(uint32_t x)
     {
-        return tail_value(x, [](uint32_t j) { return kLogTab[j][1]; });
+        return tail_value(x, [](uint32_t j) { return kLogTab[j]; });
     }
 };
 
@@ -318,11 +251,11 @@ __host__ __device__ size_t generate_lds_bytes(int M, int fp64)
 {
     // lane tables [M][16], per-wave block words [kWaves][M][2], per-wave tail
     // staging: points [kTailChunk * 64] u32 and normals [kTailChunk * 64] f64
-    // (both storage types: the normals are binary64), the logarithm table's
-    // log F column [128] f64
+    // (both storage types: the normals are binary64), the logarithm's table
+    // [64] f64, the exponential's table [64] f64
     (void)fp64;
     return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t) +
-           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 + 128 * sizeof(double);
+           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 + (64 + 64) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,6 +285,16 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     extern __shared__ uint32_t lds[];
     const int M = a.M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave's block range in scalar registers (it is the same in every
+    // lane), so each store's row address is scalar and the lane's offset a
+    // constant
+    const auto uniform_i64 = [](int64_t v) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    w0 = uniform_i64(w0);
+    w1 = uniform_i64(w1);
     uint32_t *ttab = lds;                                   // [M][16]
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
     // this wave's tail staging (see kTailChunk)
@@ -360,9 +303,13 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                                   (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * kTailChunk * 64) *
                                        sizeof(uint32_t) + 7) / 8 * 8);
     double *tz = tz0 + (size_t)wave * kTailChunk * 64;
-    // the logarithm table's log F column, for the packed tails
+    // the logarithm's table, for the packed tails
     double *ltab = tz0 + (size_t)kWaves * kTailChunk * 64;
-    for (int j = tid; j < 128; j += kWG) ltab[j] = kLogTab[j][1];
+    for (int j = tid; j < 64; j += kWG) ltab[j] = kLogTab[j];
+    // the exponential's table
+    double *etab = ltab + 64;
+    for (int j = tid; j < 64; j += kWG) etab[j] = kExpTab[j];
+    const auto etab_at = [=](uint32_t j) { return etab[j]; };
 
     if (init && WHAT == 0) {
         for (int q = tid; q < kSyncWords; q += kWG) a.sync[q] = 0u;
@@ -518,8 +465,8 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                         const double z = tl[q] ? tz[slot[q]] : zc;
                         const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * z);
                         X[n_dst] = xv;
-                        const T Sv = (T)exp_poly<true>(xv);
-                        ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
+                        const T Sv = (T)exp_tab(xv, etab_at);
+                        ((T *)a.S + ((size_t)(n_m - 1) * a.ld + ((size_t)w << 6)))[(uint32_t)lane] = valid ? Sv : Kp;
                     }
                 }
                 // the next chunk rewrites the staging only after every lane
@@ -553,8 +500,8 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             }
             const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * z);
             X[n_dst] = xv;
-            const T Sv = (T)exp_poly<true>(xv);
-            ((T *)a.S)[(size_t)(n_m - 1) * a.ld + i] = valid ? Sv : Kp;
+            const T Sv = (T)exp_tab(xv, etab_at);
+            ((T *)a.S + ((size_t)(n_m - 1) * a.ld + ((size_t)w << 6)))[(uint32_t)lane] = valid ? Sv : Kp;
         }
         if (w + 1 < w1) {
             const int c = min(__builtin_ctzll((uint64_t)w + 2u) + 6, 31);
