@@ -113,6 +113,8 @@ def parse():
                     help="serving mode: replay Poisson arrivals (200 req/s) for SECONDS")
     ap.add_argument("--serve-rate", type=float, default=200.0, metavar="REQ_PER_S",
                     help="arrival rate of the serving replay (--serve)")
+    ap.add_argument("--serve-large-tile", action="store_true",
+                    help="serve with the larger batch tile (--serve)")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="batch mode: price N options of the seeded batch workload in one call")
     ap.add_argument("--paper-estimator", action="store_true",
@@ -165,7 +167,7 @@ def time_steps(amq, pricer, p, b, w, dtype, steps, warmup):
                 price=float(res[0]), std_err=float(res[1]))
 
 
-def serve(seconds, dtype, rate=200.0):
+def serve(seconds, dtype, rate=200.0, large_tile=False):
     """Open-loop replay of seeded Poisson arrivals (`rate` req/s); each request
     is one option drawn as in the batch workload with 2^12-2^20 paths and
     12-365 dates; latency = completion - scheduled arrival (no coordinated
@@ -179,7 +181,7 @@ def serve(seconds, dtype, rate=200.0):
     b = amq.make_basis("monomial", 2)
     res = {}
     with amq.Server(64 << 30, b, dtype, n_streams=2, max_batch_requests=64,
-                    max_batch_path_steps=4e9) as srv:
+                    max_batch_path_steps=4e9, large_tile=large_tile) as srv:
         # warm-up (kernel loading, schedules) outside the measured window
         for i in range(4):
             srv.submit(opts[i], 10**9 + i)
@@ -212,7 +214,8 @@ def serve(seconds, dtype, rate=200.0):
         "data": "synthetic (seeded Poisson arrivals and option mix)",
         "config": {"workload": f"serving: Poisson {rate:g} req/s for {seconds:g} s, paths 2^12-2^20, "
                                "dates 12-365, HBM admission budget 64 GB", "requests": len(arr),
-                   "basis": "monomial degree 2"},
+                   "basis": "monomial degree 2",
+                   "batch_tile": "larger (64 paths per thread)" if large_tile else "smaller (16 paths per thread)"},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_ms": float(lat.mean() * 1e3), "completed_ok": ok, "batches": st["batches"],
         "offered_path_steps_per_s": steps / seconds,
@@ -454,7 +457,8 @@ def main():
         copy_calibration(args.copy_calibration, args.steps)
         return
     if args.serve:
-        print(json.dumps(serve(args.serve, args.dtype or "fp32", args.serve_rate)), flush=True)
+        print(json.dumps(serve(args.serve, args.dtype or "fp32", args.serve_rate, args.serve_large_tile)),
+              flush=True)
         return
     if args.batch:
         print(json.dumps(batch_run(args.batch, args.dtype or "fp32", args.steps, args.warmup)), flush=True)

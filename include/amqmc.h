@@ -327,7 +327,7 @@ typedef struct am_server_config {
     int32_t n_streams;             /* batches in flight at once (1..8) */
     am_basis basis;                /* shared by every request */
     int32_t dtype;
-    int32_t reserved;
+    int32_t large_tile;            /* 0: the smaller batch tile; 1: the larger (see am_server_create) */
 } am_server_config;
 
 typedef struct am_result {
@@ -350,8 +350,12 @@ typedef struct am_result {
  * runs alone on the whole device once every stream is idle (later requests
  * wait behind it).  Paths and cashflows stay resident in the pool until a
  * request completes.  Results are those of am_price_batch, hence identical
- * to pricing the request alone.  The batch tile is the default one (FP32
- * bulk 64 paths per thread, FP64 32), whatever am_batch_autotune chose. */
+ * to pricing the request alone with the same batch tile.  The tile is fixed
+ * per server, whatever am_batch_autotune chose: the smaller (FP32 bulk 16
+ * paths per thread, FP64 8), whose sweeps spread a request of few paths over
+ * four times the workgroups of the larger, or with large_tile the larger
+ * (64 and 32; am_price_batch's default).  Fails with AM_EINVAL for
+ * large_tile other than 0 or 1. */
 int am_server_create(const am_server_config *cfg, am_server **out);
 
 /* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now.

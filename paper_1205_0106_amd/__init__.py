@@ -53,7 +53,7 @@ class am_basis(ctypes.Structure):
 class am_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_path_steps", ctypes.c_double),
                 ("max_batch_requests", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("basis", am_basis), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("basis", am_basis), ("dtype", ctypes.c_int32), ("large_tile", ctypes.c_int32)]
 
 
 class am_result(ctypes.Structure):
@@ -402,9 +402,9 @@ class Server:
     """Continuous-batching pricing server (am_server_* through the C-ABI)."""
 
     def __init__(self, hbm_budget_bytes: int, basis: am_basis, dtype, *, n_streams: int = 2,
-                 max_batch_requests: int = 64, max_batch_path_steps: float = 2e9):
+                 max_batch_requests: int = 64, max_batch_path_steps: float = 2e9, large_tile: bool = False):
         cfg = am_server_config(int(hbm_budget_bytes), float(max_batch_path_steps),
-                               int(max_batch_requests), int(n_streams), basis, _dtype(dtype), 0)
+                               int(max_batch_requests), int(n_streams), basis, _dtype(dtype), int(large_tile))
         self._h = ctypes.c_void_p()
         _check(lib().am_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._buf = (am_result * 1024)()

@@ -108,23 +108,25 @@ def test_serving_fp32_small_paths(amq, orc):
     log(f"  worst |served - oracle| = {worst:.3e}")
 
 
+@pytest.mark.parametrize("large_tile", [False, True])
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
-def test_serving_request_larger_than_a_stream_share(amq, dtype):
+def test_serving_request_larger_than_a_stream_share(amq, dtype, large_tile):
     # eight streams: a 2^20-path request needs more sweep groups than one
     # stream's share of the device, so it runs alone on the whole device;
     # the smaller requests around it are served as usual, and every result is
-    # the batch result of the request alone (same tile)
+    # the batch result of the request alone (same tile: the server's smaller
+    # or larger one)
     b = amq.make_basis("monomial", 2)
     specs = batch_options(6, seed=37, log2_paths=(14.0, 15.0), dates=(12, 30))
     big = dict(S0=100.0, K=105.0, r=0.03, sigma=0.25, T=1.0, is_call=False, n_paths=1 << 20, n_dates=24)
     specs = specs[:2] + [big] + specs[2:4] + [dict(big, K=95.0, is_call=True)] + specs[4:]
     opts = amq.make_options(specs)
-    with amq.Server(8 << 30, b, dtype, n_streams=8, max_batch_requests=4) as srv:
+    with amq.Server(8 << 30, b, dtype, n_streams=8, max_batch_requests=4, large_tile=large_tile) as srv:
         for i in range(len(specs)):
             srv.submit(opts[i], i)
         got = _collect(srv, len(specs))
     pr = amq.Pricer(0)
-    amq.am_debug_set_batch_ppt(64 if dtype == "fp32" else 32)
+    amq.am_debug_set_batch_ppt((64 if large_tile else 16) if dtype == "fp32" else (32 if large_tile else 8))
     try:
         for i, d in enumerate(specs):
             assert got[i]["status"] == 0, (i, got[i])
