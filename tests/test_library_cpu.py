@@ -169,3 +169,14 @@ def test_batch_workspace_sizing(amq):
     assert n32 >= 4 * need and n64 >= 8 * need and n64 > n32
     bad = amq.make_options([dict(specs[0], sigma=-1.0)])
     assert amq.am_batch_workspace_bytes(bad, b, "fp32") == 0
+
+
+@pytest.mark.parametrize("field, value", [("n_streams", 0), ("n_streams", 9), ("max_batch_requests", 0),
+                                          ("dtype", 7), ("large_tile", 2), ("large_tile", -1)])
+def test_server_config_rejected_before_device(amq, field, value):
+    # the server's configuration is checked on the host, before any device call
+    cfg = amq.am_server_config(1 << 30, 2e9, 8, 2, amq.make_basis("monomial", 2), amq.AM_FP32_BULK, 0)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    assert amq.lib().am_server_create(ctypes.byref(cfg), ctypes.byref(h)) == amq.AM_EINVAL
+    assert field in amq.am_last_error() or field == "dtype"
