@@ -159,7 +159,7 @@ hipError_t preload_generate();
 hipError_t launch_sweep(const SweepArgs &a, int fp64, int wg, int ppt, hipStream_t s);
 // Workgroups of the sweep kernel that fit on one CU (0: no such kernel).
 int sweep_blocks_per_cu(int fp64, int laguerre, int wg, int ppt, int degree);
-__host__ __device__ size_t generate_lds_bytes(int M, int fp64);
+__host__ __device__ size_t generate_lds_bytes(int M, int cap);
 hipError_t launch_paper(const PaperArgs &a, int fp64, hipStream_t s);
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,

@@ -236,26 +236,66 @@ template <bool MID> __device__ __forceinline__ double inv_normal(uint32_t x)
     return MID ? inv_normal_mid_f64(x) : inv_normal_f64(x);
 }
 
-// A bridge node as the batch generator keeps it in LDS.
+// A bridge node as the batch generator keeps it in LDS: 32 bytes (date and
+// dimension in one word, the three window slots in another), so that the
+// schedule of 256 dates and the generator's tables leave room for four
+// groups per CU.
 struct LdsNode {
-    int32_t dim, m, sl, sr, dst, pad;
+    uint32_t md;    // m | dim << 16
+    uint32_t slots; // sl | sr << 8 | dst << 16
     double wl, wr, sd;
 };
+static_assert(sizeof(LdsNode) == 32, "LDS bridge node");
+static_assert(kMaxDates < 65536 && kMaxSlots <= 256, "LDS bridge node packing");
+
+// A node's integer fields, wave-uniform (scalar registers).
+struct NodeIdx { int m, dim, sl, sr, dst; };
+__device__ __forceinline__ NodeIdx node_idx(const BridgeNode &n)
+{
+    return {__builtin_amdgcn_readfirstlane(n.m), __builtin_amdgcn_readfirstlane(n.dim),
+            __builtin_amdgcn_readfirstlane(n.sl), __builtin_amdgcn_readfirstlane(n.sr),
+            __builtin_amdgcn_readfirstlane(n.dst)};
+}
+__device__ __forceinline__ NodeIdx node_idx(const LdsNode &n)
+{
+    const uint32_t md = (uint32_t)__builtin_amdgcn_readfirstlane((int)n.md);
+    const uint32_t sv = (uint32_t)__builtin_amdgcn_readfirstlane((int)n.slots);
+    return {(int)(md & 0xFFFFu), (int)(md >> 16), (int)(sv & 0xFFu), (int)((sv >> 8) & 0xFFu), (int)(sv >> 16)};
+}
 
 // Nodes whose tail normals are evaluated together (binary64 paths): a
 // 64-point Sobol block puts about 10 of its 64 points of each dimension in
 // the tails (|u - 1/2| >= 0.42), so the tails of 5 nodes mostly fill one wave.
 constexpr int kTailChunk = 5;
+// Tail points staged per wave and chunk: every lane of every node
+// (kTailFull), or kTailSmall.  An aligned block of 64 Sobol points has
+// exactly one point in each interval [k/64, (k+1)/64) of every dimension (the
+// generator matrix's leading 6 x 6 block is triangular with unit diagonal),
+// and the tails meet 12 such intervals; a wave's lanes hold 63 points of one
+// aligned block and the first of the next, so a node has at most 13 tail
+// points and a chunk at most 65 <= kTailSmall.  The smaller staging lets
+// four groups per CU hold their tables at 256 dates and more; its slots are
+// masked to the staging, so no point set could write outside it.
+constexpr int kTailFull = kTailChunk * 64, kTailSmall = 128;
+static_assert((kTailSmall & (kTailSmall - 1)) == 0 && kTailSmall >= 13 * kTailChunk, "tail staging");
 
-__host__ __device__ size_t generate_lds_bytes(int M, int fp64)
+__host__ __device__ size_t generate_lds_bytes(int M, int cap)
 {
     // lane tables [M][16], per-wave block words [kWaves][M][2], per-wave tail
-    // staging: points [kTailChunk * 64] u32 and normals [kTailChunk * 64] f64
-    // (both storage types: the normals are binary64), the logarithm's table
-    // [64] f64, the exponential's table [64] f64
-    (void)fp64;
+    // staging: points [cap] u32 and normals [cap] f64 (both storage types:
+    // the normals are binary64), the logarithm's table [64] f64, the
+    // exponential's table [64] f64
     return (size_t)M * 16 * sizeof(uint32_t) + (size_t)kWaves * M * 2 * sizeof(uint32_t) +
-           (size_t)kWaves * kTailChunk * 64 * (sizeof(uint32_t) + sizeof(double)) + 8 + (64 + 64) * sizeof(double);
+           (size_t)kWaves * cap * (sizeof(uint32_t) + sizeof(double)) + 8 + (64 + 64) * sizeof(double);
+}
+
+// The single-option generator's staging: the full one while the groups
+// that the kernel's registers allow per CU (four for binary32 storage, three
+// for binary64) still fit in LDS with it, else the smaller.
+int gen_tail_cap(int M, int fp64)
+{
+    const size_t share = (size_t)160 * 1024 / (fp64 ? 3 : 4);
+    return generate_lds_bytes(M, kTailFull) <= share ? kTailFull : kTailSmall;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,7 +316,7 @@ __host__ __device__ size_t generate_lds_bytes(int M, int fp64)
 // One workgroup's share: `init` (the group holding the option's first block)
 // writes the option's date constants and clears its barrier words; wave
 // blocks [w0, w1) are generated.
-template <typename T, int WHAT, bool MID, typename Node>
+template <typename T, int WHAT, bool MID, int CAP, typename Node>
 __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__restrict__ V,
                                          const Node *__restrict__ sched,
                                          const uint32_t *__restrict__ shift, bool init, int64_t w0,
@@ -298,13 +338,13 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     uint32_t *ttab = lds;                                   // [M][16]
     uint32_t *xw = lds + (size_t)M * 16 + (size_t)wave * M * 2;   // [M][2]
     // this wave's tail staging (see kTailChunk)
-    uint32_t *tx = lds + (size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)wave * kTailChunk * 64;
+    uint32_t *tx = lds + (size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)wave * CAP;
     double *tz0 = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) +
-                                  (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * kTailChunk * 64) *
+                                  (((size_t)M * 16 + (size_t)kWaves * M * 2 + (size_t)kWaves * CAP) *
                                        sizeof(uint32_t) + 7) / 8 * 8);
-    double *tz = tz0 + (size_t)wave * kTailChunk * 64;
+    double *tz = tz0 + (size_t)wave * CAP;
     // the logarithm's table, for the packed tails
-    double *ltab = tz0 + (size_t)kWaves * kTailChunk * 64;
+    double *ltab = tz0 + (size_t)kWaves * CAP;
     for (int j = tid; j < 64; j += kWG) ltab[j] = kLogTab[j];
     // the exponential's table
     double *etab = ltab + 64;
@@ -429,13 +469,14 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 for (int q = 0; q < kTailChunk; ++q) {
                     tl[q] = false;
                     if (s0 + q < M) {
-                        const int j = __builtin_amdgcn_readfirstlane(sched[s0 + q].dim);
+                        const int j = node_idx(sched[s0 + q]).dim;
                         const uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
                         xs[q] = x;
                         tl[q] = MoroParts<double>::tail(x);
                         const uint64_t m = __builtin_amdgcn_ballot_w64(tl[q]);
                         slot[q] = ntail + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if constexpr (CAP < kTailFull) slot[q] &= (uint32_t)(CAP - 1);
                         if (tl[q]) tx[slot[q]] = x;
                         ntail += (uint32_t)__builtin_popcountll(m);
                     }
@@ -443,9 +484,10 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (uint32_t t0 = 0; t0 < ntail; t0 += 64) {
+                const uint32_t nstaged = min(ntail, (uint32_t)CAP);
+                for (uint32_t t0 = 0; t0 < nstaged; t0 += 64) {
                     const uint32_t t = t0 + (uint32_t)lane;
-                    if (t < ntail)
+                    if (t < nstaged)
                         tz[t] = MoroParts<double>::tail_value(tx[t], [=](uint32_t j) { return ltab[j]; });
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -455,10 +497,8 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                 for (int q = 0; q < kTailChunk; ++q) {
                     if (s0 + q < M) {
                         const Node &nd = sched[s0 + q];
-                        const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
-                        const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl),
-                                  n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
-                                  n_dst = __builtin_amdgcn_readfirstlane(nd.dst);
+                        const NodeIdx ni = node_idx(nd);
+                        const int n_m = ni.m, n_sl = ni.sl, n_sr = ni.sr, n_dst = ni.dst;
                         const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr),
                                      n_sd = uniform_f64(nd.sd);
                         const double zc = MoroParts<double>::central(xs[q]);
@@ -482,10 +522,8 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
             // compiler cannot prove uniform turns every slot access into a
             // compare-and-select chain
             const Node &nd = sched[s];
-            const int j = __builtin_amdgcn_readfirstlane(nd.dim);
-            const int n_m = __builtin_amdgcn_readfirstlane(nd.m);
-            const int n_sl = __builtin_amdgcn_readfirstlane(nd.sl), n_sr = __builtin_amdgcn_readfirstlane(nd.sr),
-                      n_dst = __builtin_amdgcn_readfirstlane(nd.dst);
+            const NodeIdx ni = node_idx(nd);
+            const int j = ni.dim, n_m = ni.m, n_sl = ni.sl, n_sr = ni.sr, n_dst = ni.dst;
             const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr), n_sd = uniform_f64(nd.sd);
             uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
             if (MID) x ^= shift[j];
@@ -523,7 +561,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
 // three waves per SIMD (the packed tail evaluation needs the registers):
 // latency hiding for the per-lane dependency chain of each path through the
 // dates
-template <typename T, int WHAT, bool MID>
+template <typename T, int WHAT, bool MID, int CAP>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
            const uint32_t *__restrict__ shift)
@@ -535,29 +573,34 @@ gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restri
     if (WHAT == 0)
         for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < a.rows_n; q += (int64_t)gridDim.x * kWG)
             a.rows[q] = 0ull;
-    gen_body<T, WHAT, MID, BridgeNode>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
+    gen_body<T, WHAT, MID, CAP, BridgeNode>(a, V, sched, shift, blockIdx.x == 0, w0, w1);
 }
 
 hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
 {
     const int64_t waves = (a.nblocks + a.R - 1) / a.R;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
-    const size_t lds = generate_lds_bytes(a.M, fp64);
     const dim3 g((unsigned)grid), b(kWG);
     const bool mid = a.shift != nullptr;
+    // only the packed tails (unshifted points, paths) use the staging
+    const int cap = (a.what == 0 && !mid) ? gen_tail_cap(a.M, fp64) : kTailSmall;
+    const size_t lds = generate_lds_bytes(a.M, cap);
+    const bool full = cap == kTailFull;
     if (a.what == 0) {
         if (fp64) {
-            if (mid) hipLaunchKernelGGL((gen_kernel<double, 0, true>), g, b, lds, s, a, a.V, a.sched, a.shift);
-            else     hipLaunchKernelGGL((gen_kernel<double, 0, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            if (mid)       hipLaunchKernelGGL((gen_kernel<double, 0, true, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else if (full) hipLaunchKernelGGL((gen_kernel<double, 0, false, kTailFull>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else           hipLaunchKernelGGL((gen_kernel<double, 0, false, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
         } else {
-            if (mid) hipLaunchKernelGGL((gen_kernel<float, 0, true>), g, b, lds, s, a, a.V, a.sched, a.shift);
-            else     hipLaunchKernelGGL((gen_kernel<float, 0, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            if (mid)       hipLaunchKernelGGL((gen_kernel<float, 0, true, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else if (full) hipLaunchKernelGGL((gen_kernel<float, 0, false, kTailFull>), g, b, lds, s, a, a.V, a.sched, a.shift);
+            else           hipLaunchKernelGGL((gen_kernel<float, 0, false, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
         }
     } else if (a.what == 1) {
-        hipLaunchKernelGGL((gen_kernel<float, 1, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        hipLaunchKernelGGL((gen_kernel<float, 1, false, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
     } else {
         // the normals are binary64 for both storage types
-        hipLaunchKernelGGL((gen_kernel<double, 2, false>), g, b, lds, s, a, a.V, a.sched, a.shift);
+        hipLaunchKernelGGL((gen_kernel<double, 2, false, kTailSmall>), g, b, lds, s, a, a.V, a.sched, a.shift);
     }
     return hipGetLastError();
 }
@@ -568,8 +611,8 @@ hipError_t launch_generate(const GenArgs &a, int fp64, hipStream_t s)
 hipError_t preload_generate()
 {
     hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<float, 0, false>));
-    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<double, 0, false>));
+    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<float, 0, false, kTailFull>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&gen_kernel<double, 0, false, kTailFull>));
     return e;
 }
 
@@ -708,22 +751,23 @@ gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ 
     // the shared scalar cache, one miss per date
     extern __shared__ uint32_t lds[];
     LdsNode *nodes = reinterpret_cast<LdsNode *>(reinterpret_cast<char *>(lds) +
-                                                 (generate_lds_bytes(o.M, sizeof(T) == 8) + 15) / 16 * 16);
+                                                 (generate_lds_bytes(o.M, kTailSmall) + 15) / 16 * 16);
     for (int q = threadIdx.x; q < o.M; q += kWG) {
         const BridgeNode &b = o.sched[q];
         LdsNode n;
-        n.dim = b.dim; n.m = b.m; n.sl = b.sl; n.sr = b.sr; n.dst = b.dst; n.pad = 0;
+        n.md = (uint32_t)b.m | (uint32_t)b.dim << 16;
+        n.slots = (uint32_t)b.sl | (uint32_t)b.sr << 8 | (uint32_t)b.dst << 16;
         n.wl = b.wl; n.wr = b.wr; n.sd = b.sd;
         nodes[q] = n;
     }
-    gen_body<T, 0, MID, LdsNode>(a, V, nodes, MID ? o.shift : nullptr, u.b0 == 0, w0, w1);
+    gen_body<T, 0, MID, kTailSmall, LdsNode>(a, V, nodes, MID ? o.shift : nullptr, u.b0 == 0, w0, w1);
 }
 
 hipError_t launch_generate_batch(const BatchOpt *opts, const GenUnit *units, int n_units,
                                  const uint32_t *V, uint32_t *gsync, int max_dates, int fp64,
                                  bool shifted, hipStream_t s)
 {
-    const size_t lds = (generate_lds_bytes(max_dates, fp64) + 15) / 16 * 16 + (size_t)max_dates * sizeof(LdsNode);
+    const size_t lds = (generate_lds_bytes(max_dates, kTailSmall) + 15) / 16 * 16 + (size_t)max_dates * sizeof(LdsNode);
     const dim3 g(n_units), b(kWG);
     if (shifted) {
         // randomised QMC: every option of the batch carries its digital shift

@@ -142,3 +142,27 @@ def test_bridge_first_dimension_drives_terminal_value(orc):
     z2 = z.copy()
     z2[1:] = rng.standard_normal(M - 1)
     assert orc.bridge_apply(M, T, z)[M] == orc.bridge_apply(M, T, z2)[M]
+
+
+def test_sobol_tail_points_per_wave_are_bounded(orc):
+    # the path generator stages at most 13 tail points (|u - 1/2| >= 0.42) per
+    # dimension and wave of 64 paths (Sobol indices 64w + 1 .. 64w + 64): the
+    # leading 6 x 6 block of every dimension's generator matrix is triangular
+    # with unit diagonal (one point per interval of length 1/64 in each
+    # aligned block), and the tails meet 12 such intervals.  Checked on the
+    # matrices of all 640 dimensions and by counting points
+    V = orc.directions(640).astype(np.uint64)
+    for b in range(6):
+        # the 6 leading bits of direction number b hold 2^-1 .. 2^-(b+1):
+        # 2^-(b+1) set (odd m_b), nothing below it
+        top = V[:, b] >> np.uint64(26)
+        assert np.all((top >> np.uint64(5 - b)) & np.uint64(1) == 1), b
+        assert np.all(top & np.uint64((1 << (5 - b)) - 1) == 0), b
+    lo, hi = 0.08 * 2.0 ** 32, 0.92 * 2.0 ** 32
+    worst = 0
+    for first in (1, 64 * 37 + 1, (1 << 18) + 1):
+        pts = orc.sobol_block(640, first, 64 * 8).astype(np.float64)
+        for w in range(8):
+            blk = pts[64 * w:64 * (w + 1)]
+            worst = max(worst, int(((blk <= lo) | (blk >= hi)).sum(axis=0).max()))
+    assert worst <= 13
