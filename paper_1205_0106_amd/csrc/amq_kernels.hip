@@ -289,12 +289,13 @@ __host__ __device__ size_t generate_lds_bytes(int M, int cap)
            (size_t)kWaves * cap * (sizeof(uint32_t) + sizeof(double)) + 8 + (64 + 64) * sizeof(double);
 }
 
-// The single-option generator's staging: the full one while the groups
-// that the kernel's registers allow per CU (four for binary32 storage, three
-// for binary64) still fit in LDS with it, else the smaller.
+// The single-option generator's staging: the full one while the four groups
+// per CU that the kernel's registers allow still fit in LDS with it, else
+// the smaller.
 int gen_tail_cap(int M, int fp64)
 {
-    const size_t share = (size_t)160 * 1024 / (fp64 ? 3 : 4);
+    (void)fp64;
+    const size_t share = (size_t)160 * 1024 / 4;
     return generate_lds_bytes(M, kTailFull) <= share ? kTailFull : kTailSmall;
 }
 
@@ -558,11 +559,11 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
     }
 }
 
-// three waves per SIMD (the packed tail evaluation needs the registers):
+// four waves per SIMD (128 registers; with five the node loop spills):
 // latency hiding for the per-lane dependency chain of each path through the
 // dates
 template <typename T, int WHAT, bool MID, int CAP>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
 gen_kernel(GenArgs a, const uint32_t *__restrict__ V, const BridgeNode *__restrict__ sched,
            const uint32_t *__restrict__ shift)
 {
@@ -732,7 +733,7 @@ __device__ __forceinline__ GenArgs gen_args_of(const BatchOpt &o, const uint32_t
 }
 
 template <typename T, bool MID>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
 gen_batch_kernel(const BatchOpt *__restrict__ opts, const GenUnit *__restrict__ units,
                  const uint32_t *__restrict__ V, uint32_t *gsync)
 {
