@@ -456,14 +456,16 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
         }
         if constexpr (WHAT == 0 && !MID) {
             // the inverse normal's two branches evaluated apart (the tail's
-            // two logarithms dominate).  Every
-            // lane evaluates the (cheap) central branch; the points in the tails
-            // of kTailChunk nodes are packed into this wave's LDS staging
+            // two logarithms dominate).  Every lane evaluates the (cheap)
+            // central branch of kTailChunk nodes up front (independent of one
+            // another and of the bridge, so their latencies overlap); the
+            // points in the tails are packed into this wave's LDS staging
             // (ballot and lane rank), their tail values evaluated together,
             // one point per lane, and read back by their owners.  The values
             // are exactly those of inv_normal.
             for (int s0 = 0; s0 < M; s0 += kTailChunk) {
-                uint32_t xs[kTailChunk], slot[kTailChunk];
+                uint32_t slot[kTailChunk];
+                double zcq[kTailChunk];   // central values, computed with the tail test
                 bool tl[kTailChunk];
                 uint32_t ntail = 0;   // wave-uniform
 #pragma unroll
@@ -472,7 +474,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                     if (s0 + q < M) {
                         const int j = node_idx(sched[s0 + q]).dim;
                         const uint32_t x = xw[2 * j + xsel] ^ ttab[j * 16 + offL] ^ ttab[j * 16 + offH];
-                        xs[q] = x;
+                        zcq[q] = MoroParts<double>::central(x);
                         tl[q] = MoroParts<double>::tail(x);
                         const uint64_t m = __builtin_amdgcn_ballot_w64(tl[q]);
                         slot[q] = ntail + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -502,8 +504,7 @@ __device__ __forceinline__ void gen_body(const GenArgs &a, const uint32_t *__res
                         const int n_m = ni.m, n_sl = ni.sl, n_sr = ni.sr, n_dst = ni.dst;
                         const double n_wl = uniform_f64(nd.wl), n_wr = uniform_f64(nd.wr),
                                      n_sd = uniform_f64(nd.sd);
-                        const double zc = MoroParts<double>::central(xs[q]);
-                        const double z = tl[q] ? tz[slot[q]] : zc;
+                        const double z = tl[q] ? tz[slot[q]] : zcq[q];
                         const double xv = n_wl * X[n_sl] + n_wr * X[n_sr] + n_sd * (vol * z);
                         X[n_dst] = xv;
                         const T Sv = (T)exp_tab(xv, etab_at);
