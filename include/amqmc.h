@@ -196,8 +196,10 @@ int am_price_american_rqmc(const am_params *params, int64_t n_paths, int32_t n_d
  * am_price_batch), the mean and error bar formed on the host in the order
  * and arithmetic of am_price_american_rqmc's final step.  Replicate prices
  * agree with am_price_american_rqmc's to rounding (the tiles sum in a
- * different order).  Workspace: am_rqmc_workspace_bytes, 256-byte aligned;
- * h_out (n_rep + 2 doubles) is required; returns once the results are in. */
+ * different order).  The batch tile is the larger one while the replicates
+ * give at least one tile per compute unit at that size, else the smaller.
+ * Workspace: am_rqmc_workspace_bytes, 256-byte aligned; h_out (n_rep + 2
+ * doubles) is required; returns once the results are in. */
 int am_price_rqmc_batch(const am_params *params, int64_t n_paths, int32_t n_dates, am_basis basis,
                         int32_t dtype, int32_t n_rep, const uint32_t *h_shifts, void *d_workspace,
                         size_t ws_bytes, void *hip_stream, double *h_out);
@@ -389,9 +391,11 @@ int am_server_destroy(am_server *server);
 int am_shutdown(void);
 
 /* Tuning hook: paths per thread of the batch sweep on this thread (FP32: 16
- * or 64, FP64: 8 or 32; 0 restores the default: the larger).  Results of one option are
- * identical for a given choice; different choices change the reduction
- * order (differences at rounding level). */
+ * or 64, FP64: 8 or 32) for am_price_batch and am_price_rqmc_batch; 0
+ * restores their defaults (see each).  Servers keep the tile they were
+ * created with.  Results of one option are identical for a given choice;
+ * different choices change the reduction order (differences at rounding
+ * level). */
 void am_debug_set_batch_ppt(int32_t ppt);
 
 /* Tuning hook: allow (1, the default) or forbid (0) 512-thread workgroups in
