@@ -180,3 +180,14 @@ def test_server_config_rejected_before_device(amq, field, value):
     h = ctypes.c_void_p()
     assert amq.lib().am_server_create(ctypes.byref(cfg), ctypes.byref(h)) == amq.AM_EINVAL
     assert field in amq.am_last_error() or field == "dtype"
+
+
+def test_math_tables_match_their_definitions():
+    # the generator's logarithm and exponential tables, recomputed from their
+    # definitions at 60 digits and rounded once, equal the constants compiled
+    # into the kernels
+    import subprocess
+    import sys
+    script = os.path.join(ROOT, "paper_1205_0106_amd", "csrc", "gen_math_tables.py")
+    r = subprocess.run([sys.executable, script, "--check"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
