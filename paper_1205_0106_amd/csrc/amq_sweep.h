@@ -921,7 +921,9 @@ __device__ __forceinline__ void read_slot2(const Vec<float> *base0, const Vec<fl
 // reading LDS slot j the moment pass waits until at most the requests made
 // after slot j's are outstanding (vector memory operations complete in
 // issue order; operations the compiler adds only make the wait stricter).
-// Date constants come through scalar loads issued a date ahead.
+// Both passes read the LDS slots in pairs under one LDS wait (the moment
+// pass first waits for the pair's second load).  Date constants come
+// through scalar loads issued a date ahead.
 template <int PPT, int D, bool CALL>
 __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *__restrict__ S, uint32_t gid,
                                                const TileIO<float, PPT, 512> &io, float (&pv)[PPT], uint32_t &epoch,
@@ -1020,10 +1022,19 @@ __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *
         for (int q = 1; q < NV - 1; ++q) tv[q] = 0.0;
         double *A = tv + 1, *R = tv + NA;
         uint32_t cnt = 0;
+        Vec<float> mpend;
         static_for<0, NVEC>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             if constexpr (j + PF < NVEC) request(row, Ic<j + PF>{});
-            const Vec<float> v = slot(jc, true);
+            Vec<float> v;
+            if constexpr (j < NKL && j % 2 == 0 && j + 1 < NKL) {
+                wait_vmcnt<(PF - 1 < NVEC - 2 - j ? PF - 1 : NVEC - 2 - j)>();
+                read_slot2(resident_slot<j, NKL>(), resident_slot<j + 1, NKL>(), lane_off, v, mpend);
+            } else if constexpr (j < NKL && j % 2 == 1) {
+                v = mpend;
+            } else {
+                v = slot(jc, true);
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const bool itm = CALL ? v.v[e] > kthr : v.v[e] < kthr;
