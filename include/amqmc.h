@@ -356,8 +356,9 @@ typedef struct am_result {
  * per server, whatever am_batch_autotune chose: the smaller (FP32 bulk 16
  * paths per thread, FP64 8), whose sweeps spread a request of few paths over
  * four times the workgroups of the larger, or with large_tile the larger
- * (64 and 32; am_price_batch's default).  Fails with AM_EINVAL for
- * large_tile other than 0 or 1. */
+ * (64 and 32; am_price_batch's default), which admits requests of four times
+ * the paths (am_server_submit).  Fails with AM_EINVAL for large_tile other
+ * than 0 or 1. */
 int am_server_create(const am_server_config *cfg, am_server **out);
 
 /* Queue one request (non-blocking, thread-safe).  t_arrival < 0 means now.

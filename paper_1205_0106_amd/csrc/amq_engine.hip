@@ -831,13 +831,22 @@ int small_batch_ppt(int32_t storage) { return storage == AM_FP64 ? 8 : 16; }
 // tile per compute unit at that size, else the smaller one, so that few
 // paths still spread over the device (8 replicates of 2^17 paths in
 // binary32: 64 tiles at 64 paths per thread, 2.14 ms; 256 tiles at 16,
-// 1.46 ms).
-int shaped_batch_ppt(const am_option *opts, int32_t n, int32_t storage, int num_cu)
+// 1.46 ms) -- unless an option would then need more tiles than the device
+// holds resident.
+int shaped_batch_ppt(const am_option *opts, int32_t n, am_basis basis, int32_t storage, int num_cu)
 {
-    const int64_t tile = (int64_t)amq::kWG * default_batch_ppt(storage);
-    int64_t tiles = 0;
-    for (int i = 0; i < n; ++i) tiles += (opts[i].n_paths + tile - 1) / tile;
-    return tiles >= num_cu ? default_batch_ppt(storage) : small_batch_ppt(storage);
+    const int64_t big = (int64_t)amq::kWG * default_batch_ppt(storage);
+    const int64_t small = (int64_t)amq::kWG * small_batch_ppt(storage);
+    int64_t tiles = 0, most = 0;
+    for (int i = 0; i < n; ++i) {
+        tiles += (opts[i].n_paths + big - 1) / big;
+        const int64_t t = (opts[i].n_paths + small - 1) / small;
+        most = t > most ? t : most;
+    }
+    const int per_cu = amq::sweep_batch_blocks_per_cu(storage == AM_FP64, basis.kind == AM_BASIS_LAGUERRE,
+                                                      small_batch_ppt(storage), basis.degree);
+    const bool fits = per_cu > 0 && most <= (int64_t)per_cu * num_cu;
+    return (tiles >= num_cu || !fits) ? default_batch_ppt(storage) : small_batch_ppt(storage);
 }
 
 // Paths per thread of the sub-batch stored as `storage` in a batch the caller
@@ -1280,7 +1289,7 @@ int am_price_rqmc_batch(const am_params *params, int64_t n_paths, int32_t n_date
     int ppt[2] = {0, 0};
     for (int h = 0; h < 2; ++h)
         if (B.n(h) && !(g_batch_ppt && valid_batch_ppt(B.storage[h], g_batch_ppt)))
-            ppt[h] = shaped_batch_ppt(B.opts[h].data(), B.n(h), B.storage[h], st->num_cu);
+            ppt[h] = shaped_batch_ppt(B.opts[h].data(), B.n(h), basis, B.storage[h], st->num_cu);
     rc = enqueue_split(st, B, basis, dtype, ws, stream, nullptr, true, nullptr, 0, ppt, shifts.data());
     if (rc) return rc;
     std::vector<double> res(split_results_doubles(B)), pr(2 * (size_t)n_rep);
