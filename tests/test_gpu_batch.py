@@ -188,3 +188,28 @@ def test_batch_fp32_many_dates_ill_conditioned(amq, orc, pricer):
         single = pricer.price(p, d["n_paths"], d["n_dates"], b, "fp32")[0]
         want = _want(amq, orc, d, "fp32")
         assert abs(single - want.price) <= TOL["fp32"], (pick[j], single, want.price)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batch_long_date_counts(amq, orc, pricer, dtype):
+    # options up to the engine's date limit in one batch with a short one:
+    # the generator's LDS then holds the longest option's lane tables, block
+    # words and schedule (compact tail staging, fewer groups per CU); every
+    # option still meets the oracle, and the short one prices as it does alone.
+    # (r = sigma^2 / 2 with S0 = K would put paths exactly at the strike:
+    # test_gpu_parity.py::test_zero_drift_at_the_money_ties covers that case.)
+    n = 1 << 14
+    mmax = amq.am_max_dates()
+    specs = [dict(S0=100.0, K=105.0, r=0.03, sigma=0.25, T=1.0, is_call=False, n_paths=n, n_dates=mmax),
+             dict(S0=100.0, K=95.0, r=0.05, sigma=0.3, T=2.0, is_call=True, n_paths=n, n_dates=400),
+             dict(S0=100.0, K=100.0, r=0.03, sigma=0.2, T=0.5, is_call=False, n_paths=2 * n, n_dates=300),
+             dict(S0=100.0, K=110.0, r=0.04, sigma=0.35, T=1.5, is_call=False, n_paths=n, n_dates=12)]
+    b = amq.make_basis("monomial", 2)
+    log(f"  batch with {mmax}, 400, 300 and 12 dates ({dtype})")
+    got = pricer.price_batch(amq.make_options(specs), b, dtype)
+    for i, d in enumerate(specs):
+        want = _want(amq, orc, d, dtype)
+        log(f"    opt {i}: N={d['n_paths']} M={d['n_dates']} gpu {got[i, 0]:.8f} oracle {want.price:.8f}")
+        assert abs(got[i, 0] - want.price) <= TOL[dtype], (i, got[i], want.price)
+    alone = pricer.price_batch(amq.make_options([specs[3]]), b, dtype)
+    assert alone[0, 0] == got[3, 0] and alone[0, 1] == got[3, 1]

@@ -185,6 +185,37 @@ def test_config1_price_and_paths(amq, orc, pricer, dtype):
     assert bad.mean() <= 1e-3
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_zero_drift_at_the_money_ties(amq, orc, pricer, dtype):
+    # S0 = K and r = sigma^2 / 2: the log-price drift is zero, so every path
+    # whose bridge noise is zero at a date (Sobol coordinates exactly 1/2)
+    # sits exactly at the strike there, and its in-the-money test (h > 0
+    # strictly) is decided by the last ulp of the exponential, which differs
+    # between the kernel's and the C library's.  Such a tie moves the
+    # regression of its date and, through it, decisions of other paths, so
+    # the parity that is unique here is: the paths agree to rounding, and the
+    # backward induction on the kernel's own paths is the oracle's.
+    N, M = 1 << 15, 40
+    prm = dict(S0=100.0, K=100.0, r=0.02, sigma=0.2, T=0.5)
+    p = amq.make_params(**prm)
+    b = amq.make_basis("monomial", 2)
+    price = pricer.price(p, N, M, b, dtype)[0]
+    v = pricer.views(N, M, b, dtype)
+    S = v["S"].cpu().numpy().astype(np.float64)
+    want = orc.paths(**prm, N=N, M=M)
+    if dtype == "fp32":
+        check_stored32(S, want, "zero-drift paths")
+    else:
+        assert (np.abs(S - want) / want).max() <= 1e-12
+    ties = int((np.abs(want - prm["K"]) <= 1e-12 * prm["K"]).sum())
+    same = orc.lsm_on_paths(S, **prm, kind=orc.MONOMIAL, degree=2, store32=(dtype == "fp32"))
+    own = orc.price_american(**prm, N=N, M=M, kind=orc.MONOMIAL, degree=2, store32=(dtype == "fp32"))
+    log(f"  {dtype}: {ties} path-dates at the strike; gpu {price:.10f}, oracle on the gpu's paths "
+        f"{same.price:.10f}, oracle on its own paths {own.price:.10f}")
+    assert ties > 0
+    assert abs(price - same.price) <= (1e-10 if dtype == "fp64" else 1e-7)
+
+
 def golden(cid, dtype):
     """Stored oracle results for a full-size configuration (written by
     tests/golden/make_oracle_goldens.py, which calls only the oracle): the
