@@ -191,3 +191,21 @@ def test_math_tables_match_their_definitions():
     script = os.path.join(ROOT, "paper_1205_0106_amd", "csrc", "gen_math_tables.py")
     r = subprocess.run([sys.executable, script, "--check"], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary header compiles as ISO C99 (no C++ or HIP types), so any C
+    # caller can use it
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "amqmc.h"\n'
+                   "int use(void) { am_server_config c = {0}; am_params p = {0};\n"
+                   "  (void)c; (void)p; return am_max_dates(); }\n")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "u.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
