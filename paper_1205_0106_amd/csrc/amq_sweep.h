@@ -907,6 +907,29 @@ __device__ __forceinline__ void read_slot2(const Vec<float> *base0, const Vec<fl
     v1.v[0] = r1.x; v1.v[1] = r1.y; v1.v[2] = r1.z; v1.v[3] = r1.w;
 }
 
+// Four 16-byte LDS reads under one wait, complete on return.
+__device__ __forceinline__ void read_slot4(const Vec<float> *base0, const Vec<float> *base1,
+                                           const Vec<float> *base2, const Vec<float> *base3, uint32_t lane_off,
+                                           Vec<float> &v0, Vec<float> &v1, Vec<float> &v2, Vec<float> &v3)
+{
+    using V4 = float __attribute__((ext_vector_type(4)));
+    const uint32_t b0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base0;
+    const uint32_t b1 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base1;
+    const uint32_t b2 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base2;
+    const uint32_t b3 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)base3;
+    V4 r0, r1, r2, r3;
+    uint32_t t0, t1, t2, t3;
+    asm volatile("v_add_u32 %4, %8, %12\n\tv_add_u32 %5, %9, %12\n\tv_add_u32 %6, %10, %12\n\t"
+                 "v_add_u32 %7, %11, %12\n\tds_read_b128 %0, %4\n\tds_read_b128 %1, %5\n\t"
+                 "ds_read_b128 %2, %6\n\tds_read_b128 %3, %7\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3)
+                 : "s"(b0), "s"(b1), "s"(b2), "s"(b3), "v"(lane_off));
+    v0.v[0] = r0.x; v0.v[1] = r0.y; v0.v[2] = r0.z; v0.v[3] = r0.w;
+    v1.v[0] = r1.x; v1.v[1] = r1.y; v1.v[2] = r1.z; v1.v[3] = r1.w;
+    v2.v[0] = r2.x; v2.v[1] = r2.y; v2.v[2] = r2.z; v2.v[3] = r2.w;
+    v3.v[0] = r3.x; v3.v[1] = r3.y; v3.v[2] = r3.z; v3.v[3] = r3.w;
+}
+
 // Slab-resident tile: per date, a moment pass over the slab, the
 // device-wide sum and solve, then the exercise update over the same values.
 // A thread's 4-path vectors ("slots", j = 0..NVEC-1) are processed in the
@@ -921,8 +944,8 @@ __device__ __forceinline__ void read_slot2(const Vec<float> *base0, const Vec<fl
 // reading LDS slot j the moment pass waits until at most the requests made
 // after slot j's are outstanding (vector memory operations complete in
 // issue order; operations the compiler adds only make the wait stricter).
-// Both passes read the LDS slots in pairs under one LDS wait (the moment
-// pass first waits for the pair's second load).  Date constants come
+// Both passes read the LDS slots in fours (then a pair and a single) under
+// one LDS wait each (the moment pass first waits for the group's last load).  Date constants come
 // through scalar loads issued a date ahead.
 template <int PPT, int D, bool CALL>
 __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *__restrict__ S, uint32_t gid,
@@ -1022,15 +1045,22 @@ __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *
         for (int q = 1; q < NV - 1; ++q) tv[q] = 0.0;
         double *A = tv + 1, *R = tv + NA;
         uint32_t cnt = 0;
-        Vec<float> mpend;
+        Vec<float> mpend, mq[3];
+        constexpr int NQ = NKL / 4 * 4;
         static_for<0, NVEC>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             if constexpr (j + PF < NVEC) request(row, Ic<j + PF>{});
             Vec<float> v;
-            if constexpr (j < NKL && j % 2 == 0 && j + 1 < NKL) {
+            if constexpr (j < NQ && j % 4 == 0) {
+                wait_vmcnt<(PF - 3 < NVEC - 4 - j ? PF - 3 : NVEC - 4 - j)>();
+                read_slot4(resident_slot<j, NKL>(), resident_slot<j + 1, NKL>(), resident_slot<j + 2, NKL>(),
+                           resident_slot<j + 3, NKL>(), lane_off, v, mq[0], mq[1], mq[2]);
+            } else if constexpr (j < NQ) {
+                v = mq[j % 4 - 1];
+            } else if constexpr (j < NKL && (j - NQ) % 2 == 0 && j + 1 < NKL) {
                 wait_vmcnt<(PF - 1 < NVEC - 2 - j ? PF - 1 : NVEC - 2 - j)>();
                 read_slot2(resident_slot<j, NKL>(), resident_slot<j + 1, NKL>(), lane_off, v, mpend);
-            } else if constexpr (j < NKL && j % 2 == 1) {
+            } else if constexpr (j < NKL && (j - NQ) % 2 == 1) {
                 v = mpend;
             } else {
                 v = slot(jc, true);
@@ -1074,16 +1104,23 @@ __device__ __forceinline__ void sweep_resident(const SweepArgs &a, const float *
         const double dsg = dk * sg, dnsk = dk * nsk;
         // the next date's slab (the last date requests date 1 again, unused)
         const float *nrow = S + (size_t)(k >= 2 ? k - 2 : 0) * ld;
-        // LDS slots in pairs: the even slot's read also fetches the next one
-        Vec<float> pend;
+        // LDS slots in fours, then a pair: the first slot's read also fetches
+        // the next ones
+        Vec<float> pend, uq[3];
+        constexpr int UQ = NKL / 4 * 4;
         static_for<0, NVEC>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
             // the re-read slots again, PF ahead
             if constexpr (t + PF >= NKL + NKR && t + PF < NVEC) request(row, Ic<t + PF>{});
             Vec<float> v;
-            if constexpr (t < NKL && t % 2 == 0 && t + 1 < NKL) {
+            if constexpr (t < UQ && t % 4 == 0) {
+                read_slot4(resident_slot<t, NKL>(), resident_slot<t + 1, NKL>(), resident_slot<t + 2, NKL>(),
+                           resident_slot<t + 3, NKL>(), lane_off, v, uq[0], uq[1], uq[2]);
+            } else if constexpr (t < UQ) {
+                v = uq[t % 4 - 1];
+            } else if constexpr (t < NKL && (t - UQ) % 2 == 0 && t + 1 < NKL) {
                 read_slot2(resident_slot<t, NKL>(), resident_slot<t + 1, NKL>(), lane_off, v, pend);
-            } else if constexpr (t < NKL && t % 2 == 1) {
+            } else if constexpr (t < NKL && (t - UQ) % 2 == 1) {
                 v = pend;
             } else {
                 v = slot(tc, false);
